@@ -1,0 +1,527 @@
+// FP64 CPU oracle for the exponential-kernel multi-dimensional Hawkes
+// process (MDHP) log-likelihood, its gradient and the projected gradient
+// fit.  TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the
+// bench's cpu_baseline leg call it; the product path never does.  It shares
+// no source with the GPU library.
+//
+// What it computes (paper: "MDHP-Net", Sec. II-B and Sec. IV-B):
+//   intensity, Eq. (2):
+//     lambda_m(t) = mu_m + sum_n sum_{k: d_k = n, t_k < t} alpha_mn e^{-beta_mn (t - t_k)}
+//   closed-form log-likelihood, Eq. (5) (Part1 + Part2 + Part3, Appendix B):
+//     ll = sum_i log lambda_{d_i}(t_i) - T sum_m mu_m
+//          + sum_{m,n} (alpha_mn / beta_mn) sum_{k: d_k = n} (e^{-beta_mn (T - t_k)} - 1)
+//   Notation: the paper's theta is mu, its D is M, its T_span is T.  alpha_mn
+//   is the excitation of target m by source n (the direction the formula of
+//   Eq. (2) gives; the prose under Eq. (2) states the opposite, and the
+//   formula is taken).  Events at equal times never excite each other: the
+//   inner sum of Eq. (2) and Eq. (5) is over strictly earlier times.
+//
+// Three independent evaluations:
+//   * brute:     Eq. (5) written out, O(N^2) per window (tiny inputs).
+//   * recursion: the same sums with Part1's inner double sum replaced by the
+//                standard exponential-kernel recursion (Ozaki, cited by the
+//                paper for Eq. (1)), O(N M^2) per window; exact up to rounding.
+//   * fit:       projected gradient ascent on ll / max(N, 1) (plain step or
+//                Adam step), projection mu >= mu_min, alpha >= 0,
+//                beta >= beta_min; the paper uses "a PyTorch optimizer" on
+//                -ll without naming it (Sec. IV-B), so the update rule is a
+//                stated reading, not the paper's.
+//
+// Layouts (host memory, caller-owned):
+//   offsets int64[W+1]; window w owns events [offsets[w], offsets[w+1])
+//   t f64[sum N]  non-decreasing within a window, 0 <= t <= T[w]
+//   dim i32[sum N] in [0, M)
+//   T f64[W] > 0
+//   mu f64[W*M]; alpha f64[W*M*M] row-major, alpha[w][m][n] = source n -> target m
+//   beta f64[W] (beta_mode 0, one decay per window) or f64[W*M*M] (beta_mode 1)
+// Return codes: 0 ok, -1 invalid argument, -2 unsorted times, -3 t/dim/T out
+// of domain, -4 bad parameter (mu <= 0, alpha < 0, beta <= 0 or non-finite).
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+namespace {
+
+struct Window {
+  const double* t;
+  const int32_t* d;
+  int64_t n;
+  double T;
+};
+
+// One window's parameters expanded to M x M decays (a shared decay is copied
+// into every pair; nothing else differs between the two modes).
+struct Params {
+  int M;
+  std::vector<double> mu, alpha, beta;  // M, M*M, M*M
+};
+
+Params load_params(int M, int beta_mode, const double* mu, const double* alpha,
+                   const double* beta, int64_t w) {
+  Params p;
+  p.M = M;
+  p.mu.assign(mu + w * M, mu + (w + 1) * M);
+  p.alpha.assign(alpha + w * M * M, alpha + (w + 1) * M * M);
+  p.beta.resize((size_t)M * M);
+  for (int i = 0; i < M * M; ++i)
+    p.beta[i] = beta_mode == 0 ? beta[w] : beta[w * M * M + i];
+  return p;
+}
+
+int check_params(const Params& p) {
+  const int M = p.M;
+  for (int m = 0; m < M; ++m)
+    if (!(p.mu[m] > 0.0) || !std::isfinite(p.mu[m])) return -4;
+  for (int i = 0; i < M * M; ++i) {
+    if (!(p.alpha[i] >= 0.0) || !std::isfinite(p.alpha[i])) return -4;
+    if (!(p.beta[i] > 0.0) || !std::isfinite(p.beta[i])) return -4;
+  }
+  return 0;
+}
+
+int check_batch(const int64_t* offsets, const double* t, const int32_t* dim,
+                const double* T, int64_t W, int M) {
+  if (W < 0 || M < 1 || !offsets || !T) return -1;
+  if (offsets[0] != 0) return -1;
+  for (int64_t w = 0; w < W; ++w) {
+    if (offsets[w + 1] < offsets[w]) return -1;
+    if (!(T[w] > 0.0) || !std::isfinite(T[w])) return -3;
+    for (int64_t i = offsets[w]; i < offsets[w + 1]; ++i) {
+      if (!(t[i] >= 0.0) || !(t[i] <= T[w])) return -3;
+      if (dim[i] < 0 || dim[i] >= M) return -3;
+      if (i > offsets[w] && t[i] < t[i - 1]) return -2;
+    }
+  }
+  return 0;
+}
+
+// Runs f(w) for every window on a pool of host threads; windows are handed
+// out dynamically so that uneven window sizes balance.
+template <class F>
+void for_windows(int64_t W, int nthreads, F f) {
+  if (nthreads <= 0) nthreads = (int)std::max(1u, std::thread::hardware_concurrency());
+  nthreads = (int)std::min<int64_t>(nthreads, std::max<int64_t>(W, 1));
+  std::atomic<int64_t> next{0};
+  auto worker = [&]() {
+    for (;;) {
+      int64_t w = next.fetch_add(1);
+      if (w >= W) break;
+      f(w);
+    }
+  };
+  if (nthreads == 1) {
+    worker();
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int i = 0; i < nthreads; ++i) pool.emplace_back(worker);
+  for (auto& th : pool) th.join();
+}
+
+// Gradient container (same layout as the parameters, per-pair decays).
+struct Grad {
+  std::vector<double> mu, alpha, beta;
+};
+
+// Magnitudes that set parity tolerances: sum_i |log lambda_i| + Gamma for
+// ll, and for every gradient component the sum of the absolute values of the
+// terms whose signed sum it is.
+struct Scale {
+  double ll = 0.0;
+  std::vector<double> mu, alpha, beta;
+};
+
+// ---------------------------------------------------------------------------
+// Brute force: Eq. (5) term by term.  Part1 = sum over events of the log of
+// Eq. (2) at the event, with the inner sum over every strictly earlier event;
+// Part2 = -T sum mu; Part3 = sum_{m,n} alpha_mn/beta_mn sum_{k: d_k=n}
+// (e^{-beta_mn (T - t_k)} - 1) (with the "-1" of Eq. (5) and Appendix B).
+// The gradient is the term-by-term derivative of the same expression.
+// ---------------------------------------------------------------------------
+double brute_window(const Window& win, const Params& p, Grad* g) {
+  const int M = p.M;
+  if (g) {
+    g->mu.assign(M, 0.0);
+    g->alpha.assign((size_t)M * M, 0.0);
+    g->beta.assign((size_t)M * M, 0.0);
+  }
+  double part1 = 0.0;
+  for (int64_t i = 0; i < win.n; ++i) {
+    const int m = win.d[i];
+    double lam = p.mu[m];
+    for (int64_t k = 0; k < win.n; ++k) {
+      if (!(win.t[k] < win.t[i])) continue;
+      const int n = win.d[k];
+      lam += p.alpha[m * M + n] * std::exp(-p.beta[m * M + n] * (win.t[i] - win.t[k]));
+    }
+    part1 += std::log(lam);
+    if (g) {
+      const double w = 1.0 / lam;
+      g->mu[m] += w;
+      for (int64_t k = 0; k < win.n; ++k) {
+        if (!(win.t[k] < win.t[i])) continue;
+        const int n = win.d[k];
+        const double u = win.t[i] - win.t[k];
+        const double e = std::exp(-p.beta[m * M + n] * u);
+        g->alpha[m * M + n] += w * e;
+        g->beta[m * M + n] += -w * p.alpha[m * M + n] * u * e;
+      }
+    }
+  }
+  double sum_mu = 0.0;
+  for (int m = 0; m < M; ++m) sum_mu += p.mu[m];
+  const double part2 = -win.T * sum_mu;
+  double part3 = 0.0;
+  for (int m = 0; m < M; ++m) {
+    for (int n = 0; n < M; ++n) {
+      const double a = p.alpha[m * M + n], b = p.beta[m * M + n];
+      double s = 0.0, s_tau = 0.0;  // sum (e^{-b tau} - 1), sum tau e^{-b tau}
+      for (int64_t k = 0; k < win.n; ++k) {
+        if (win.d[k] != n) continue;
+        const double tau = win.T - win.t[k];
+        s += std::expm1(-b * tau);
+        s_tau += tau * std::exp(-b * tau);
+      }
+      part3 += a / b * s;
+      if (g) {
+        g->alpha[m * M + n] += s / b;
+        // d/db [a/b * s(b)] = -a/b^2 s + a/b * ds/db, ds/db = -sum tau e^{-b tau}
+        g->beta[m * M + n] += -a / (b * b) * s - a / b * s_tau;
+      }
+    }
+  }
+  if (g)
+    for (int m = 0; m < M; ++m) g->mu[m] -= win.T;
+  return part1 + part2 + part3;
+}
+
+// ---------------------------------------------------------------------------
+// Recursion: Part1's inner sum R_mn(i) = sum_{k: d_k=n, t_k<t_i}
+// e^{-beta_mn (t_i - t_k)} follows R(i) = e^{-beta Dt} (R(i') + P) where i'
+// is the last event strictly before t_i and P counts the events at t_{i'}
+// (events that share a time stay "pending" until time moves on, so they
+// never excite each other).  S_mn(i) = sum (t_i - t_k) e^{-beta_mn (t_i -
+// t_k)} = -dR/dbeta follows S(i) = e^{-beta Dt} S(i') + Dt R(i).  Part2 and
+// Part3 are summed per event exactly as in the brute form.
+// ---------------------------------------------------------------------------
+double recursion_window(const Window& win, const Params& p, Grad* g, Scale* sc = nullptr) {
+  const int M = p.M;
+  const int MM = M * M;
+  std::vector<double> R(MM, 0.0), S(MM, 0.0), pend(M, 0.0);
+  std::vector<double> gR(MM, 0.0), gS(MM, 0.0), gmu(M, 0.0);
+  double t_prev = 0.0;
+  double part1 = 0.0, abs1 = 0.0;
+  for (int64_t i = 0; i < win.n; ++i) {
+    const double dt = win.t[i] - t_prev;
+    if (dt > 0.0) {
+      for (int m = 0; m < M; ++m)
+        for (int n = 0; n < M; ++n) {
+          const double a = std::exp(-p.beta[m * M + n] * dt);
+          const double r = a * (R[m * M + n] + pend[n]);
+          S[m * M + n] = a * S[m * M + n] + dt * r;
+          R[m * M + n] = r;
+        }
+      std::fill(pend.begin(), pend.end(), 0.0);
+      t_prev = win.t[i];
+    }
+    const int m = win.d[i];
+    double lam = p.mu[m];
+    for (int n = 0; n < M; ++n) lam += p.alpha[m * M + n] * R[m * M + n];
+    part1 += std::log(lam);
+    abs1 += std::fabs(std::log(lam));
+    if (g || sc) {
+      const double w = 1.0 / lam;
+      gmu[m] += w;
+      for (int n = 0; n < M; ++n) {
+        gR[m * M + n] += w * R[m * M + n];
+        gS[m * M + n] += w * S[m * M + n];
+      }
+    }
+    pend[m] += 1.0;
+  }
+  double sum_mu = 0.0;
+  for (int m = 0; m < M; ++m) sum_mu += p.mu[m];
+  const double part2 = -win.T * sum_mu;
+  // Part3, one event at a time: for every source event k and every target m.
+  std::vector<double> s(MM, 0.0), s_tau(MM, 0.0);
+  for (int64_t k = 0; k < win.n; ++k) {
+    const int n = win.d[k];
+    const double tau = win.T - win.t[k];
+    for (int m = 0; m < M; ++m) {
+      const double b = p.beta[m * M + n];
+      s[m * M + n] += std::expm1(-b * tau);
+      s_tau[m * M + n] += tau * std::exp(-b * tau);
+    }
+  }
+  double part3 = 0.0;
+  for (int i = 0; i < MM; ++i) part3 += p.alpha[i] / p.beta[i] * s[i];
+  if (sc) {
+    // Gamma = T sum mu + sum alpha/beta sum (1 - e^{-beta tau}) >= 0.
+    sc->ll = abs1 + win.T * sum_mu - part3;
+    sc->mu.resize(M);
+    sc->alpha.resize(MM);
+    sc->beta.resize(MM);
+    for (int m = 0; m < M; ++m) sc->mu[m] = gmu[m] + win.T;
+    for (int i = 0; i < MM; ++i) {
+      const double a = p.alpha[i], b = p.beta[i];
+      sc->alpha[i] = gR[i] + std::fabs(s[i]) / b;
+      sc->beta[i] = a * gS[i] + a / (b * b) * std::fabs(s[i]) + a / b * s_tau[i];
+    }
+  }
+  if (g) {
+    g->mu.resize(M);
+    g->alpha.resize(MM);
+    g->beta.resize(MM);
+    for (int m = 0; m < M; ++m) g->mu[m] = gmu[m] - win.T;
+    for (int i = 0; i < MM; ++i) {
+      const double a = p.alpha[i], b = p.beta[i];
+      g->alpha[i] = gR[i] + s[i] / b;
+      g->beta[i] = -a * gS[i] - a / (b * b) * s[i] - a / b * s_tau[i];
+    }
+  }
+  return part1 + part2 + part3;
+}
+
+void store_grad(const Grad& g, int M, int beta_mode, int64_t w, double* g_mu,
+                double* g_alpha, double* g_beta) {
+  const int MM = M * M;
+  if (g_mu) std::copy(g.mu.begin(), g.mu.end(), g_mu + w * M);
+  if (g_alpha) std::copy(g.alpha.begin(), g.alpha.end(), g_alpha + w * MM);
+  if (g_beta) {
+    if (beta_mode == 0) {
+      // One shared decay: the chain rule sums the per-pair derivatives.
+      double sb = 0.0;
+      for (int i = 0; i < MM; ++i) sb += g.beta[i];
+      g_beta[w] = sb;
+    } else {
+      std::copy(g.beta.begin(), g.beta.end(), g_beta + w * MM);
+    }
+  }
+}
+
+template <bool kBrute>
+int eval_batch(const int64_t* offsets, const double* t, const int32_t* dim,
+               const double* T, int64_t W, int32_t M, int32_t beta_mode,
+               const double* mu, const double* alpha, const double* beta,
+               double* ll, double* g_mu, double* g_alpha, double* g_beta,
+               int32_t nthreads) {
+  if (beta_mode != 0 && beta_mode != 1) return -1;
+  if (!mu || !alpha || !beta || !ll) return -1;
+  int rc = check_batch(offsets, t, dim, T, W, M);
+  if (rc) return rc;
+  for (int64_t w = 0; w < W; ++w) {
+    rc = check_params(load_params(M, beta_mode, mu, alpha, beta, w));
+    if (rc) return rc;
+  }
+  const bool want_grad = g_mu || g_alpha || g_beta;
+  for_windows(W, nthreads, [&](int64_t w) {
+    Window win{t + offsets[w], dim + offsets[w], offsets[w + 1] - offsets[w], T[w]};
+    Params p = load_params(M, beta_mode, mu, alpha, beta, w);
+    Grad g;
+    ll[w] = kBrute ? brute_window(win, p, want_grad ? &g : nullptr)
+                   : recursion_window(win, p, want_grad ? &g : nullptr);
+    if (want_grad) store_grad(g, M, beta_mode, w, g_mu, g_alpha, g_beta);
+  });
+  return 0;
+}
+
+// Options of the projected gradient fit; same field order as the library's
+// public struct so that one Python packing serves both (declared separately:
+// the two share no source).
+struct FitOpts {
+  int32_t max_steps;
+  int32_t optimizer;  // 0 = projected gradient step, 1 = projected Adam step
+  int32_t fix_beta;
+  int32_t reserved;
+  double lr;
+  double ll_tol;
+  double mu_floor_rel;
+  double beta_floor_rel;
+  double adam_b1, adam_b2, adam_eps;
+};
+
+}  // namespace
+
+extern "C" {
+
+int mdhp_oracle_loglik(const int64_t* offsets, const double* t, const int32_t* dim,
+                       const double* T, int64_t W, int32_t M, int32_t beta_mode,
+                       const double* mu, const double* alpha, const double* beta,
+                       double* ll, int32_t nthreads) {
+  return eval_batch<false>(offsets, t, dim, T, W, M, beta_mode, mu, alpha, beta, ll,
+                           nullptr, nullptr, nullptr, nthreads);
+}
+
+int mdhp_oracle_grad(const int64_t* offsets, const double* t, const int32_t* dim,
+                     const double* T, int64_t W, int32_t M, int32_t beta_mode,
+                     const double* mu, const double* alpha, const double* beta,
+                     double* ll, double* g_mu, double* g_alpha, double* g_beta,
+                     int32_t nthreads) {
+  if (!g_mu || !g_alpha || !g_beta) return -1;
+  return eval_batch<false>(offsets, t, dim, T, W, M, beta_mode, mu, alpha, beta, ll,
+                           g_mu, g_alpha, g_beta, nthreads);
+}
+
+int mdhp_oracle_loglik_brute(const int64_t* offsets, const double* t, const int32_t* dim,
+                             const double* T, int64_t W, int32_t M, int32_t beta_mode,
+                             const double* mu, const double* alpha, const double* beta,
+                             double* ll, int32_t nthreads) {
+  return eval_batch<true>(offsets, t, dim, T, W, M, beta_mode, mu, alpha, beta, ll,
+                          nullptr, nullptr, nullptr, nthreads);
+}
+
+int mdhp_oracle_grad_brute(const int64_t* offsets, const double* t, const int32_t* dim,
+                           const double* T, int64_t W, int32_t M, int32_t beta_mode,
+                           const double* mu, const double* alpha, const double* beta,
+                           double* ll, double* g_mu, double* g_alpha, double* g_beta,
+                           int32_t nthreads) {
+  if (!g_mu || !g_alpha || !g_beta) return -1;
+  return eval_batch<true>(offsets, t, dim, T, W, M, beta_mode, mu, alpha, beta, ll,
+                          g_mu, g_alpha, g_beta, nthreads);
+}
+
+// Projected gradient ascent per window.  Step s = 0, 1, ...: evaluate ll_s
+// and the gradient g_s at theta_s (recursion form); stop as converged when
+// s >= 1 and |ll_s - ll_{s-1}| <= ll_tol * max(|ll_s|, 1); stop as not
+// converged when s == max_steps; otherwise theta_{s+1} = Proj(theta_s +
+// step(g_s / max(N, 1))).  The returned theta is theta_s with ll_s, and
+// steps[w] = s (the number of updates applied).  status: 0 converged,
+// 1 step budget exhausted, 2 non-finite likelihood or gradient (theta_s,
+// the parameters of that evaluation, is returned with its ll).
+int mdhp_oracle_fit(const int64_t* offsets, const double* t, const int32_t* dim,
+                    const double* T, int64_t W, int32_t M, int32_t beta_mode,
+                    const void* opts_ptr, double* mu, double* alpha, double* beta,
+                    double* ll, int32_t* steps, int32_t* status, int32_t nthreads) {
+  if (beta_mode != 0 && beta_mode != 1) return -1;
+  if (!opts_ptr || !mu || !alpha || !beta || !ll || !steps || !status) return -1;
+  FitOpts o;
+  std::memcpy(&o, opts_ptr, sizeof(o));
+  if (o.max_steps < 0 || !(o.lr > 0.0) || (o.optimizer != 0 && o.optimizer != 1)) return -1;
+  int rc = check_batch(offsets, t, dim, T, W, M);
+  if (rc) return rc;
+  for (int64_t w = 0; w < W; ++w) {
+    rc = check_params(load_params(M, beta_mode, mu, alpha, beta, w));
+    if (rc) return rc;
+  }
+  const int MM = M * M;
+  const int nb = beta_mode == 0 ? 1 : MM;
+  for_windows(W, nthreads, [&](int64_t w) {
+    Window win{t + offsets[w], dim + offsets[w], offsets[w + 1] - offsets[w], T[w]};
+    const double rate = (double)std::max<int64_t>(win.n, 1) / win.T;
+    const double mu_min = o.mu_floor_rel * rate;
+    const double beta_min = o.beta_floor_rel * rate;
+    const double inv_n = 1.0 / (double)std::max<int64_t>(win.n, 1);
+    // theta as one vector: [mu (M) | alpha (MM) | beta (nb)]
+    const int P = M + MM + nb;
+    std::vector<double> th(P), m1(P, 0.0), m2(P, 0.0), gv(P);
+    std::copy(mu + w * M, mu + (w + 1) * M, th.begin());
+    std::copy(alpha + w * MM, alpha + (w + 1) * MM, th.begin() + M);
+    if (beta_mode == 0) th[M + MM] = beta[w];
+    else std::copy(beta + w * MM, beta + (w + 1) * MM, th.begin() + M + MM);
+    double ll_prev = 0.0;
+    int st = 1, s = 0;
+    std::vector<double> th_eval = th;
+    double ll_eval = 0.0;
+    for (s = 0;; ++s) {
+      Params p;
+      p.M = M;
+      p.mu.assign(th.begin(), th.begin() + M);
+      p.alpha.assign(th.begin() + M, th.begin() + M + MM);
+      p.beta.resize(MM);
+      for (int i = 0; i < MM; ++i) p.beta[i] = beta_mode == 0 ? th[M + MM] : th[M + MM + i];
+      Grad g;
+      const double l = recursion_window(win, p, &g);
+      bool finite = std::isfinite(l);
+      std::copy(g.mu.begin(), g.mu.end(), gv.begin());
+      std::copy(g.alpha.begin(), g.alpha.end(), gv.begin() + M);
+      if (beta_mode == 0) {
+        double sb = 0.0;
+        for (int i = 0; i < MM; ++i) sb += g.beta[i];
+        gv[M + MM] = sb;
+      } else {
+        std::copy(g.beta.begin(), g.beta.end(), gv.begin() + M + MM);
+      }
+      for (int i = 0; i < P; ++i) finite = finite && std::isfinite(gv[i]);
+      if (!finite) {
+        st = 2;  // returns the parameters whose evaluation was not finite
+        th_eval = th;
+        ll_eval = l;
+        break;
+      }
+      th_eval = th;
+      ll_eval = l;
+      if (s >= 1 && std::fabs(l - ll_prev) <= o.ll_tol * std::max(std::fabs(l), 1.0)) {
+        st = 0;
+        break;
+      }
+      if (s == o.max_steps) {
+        st = 1;
+        break;
+      }
+      ll_prev = l;
+      const double bc1 = 1.0 - std::pow(o.adam_b1, (double)(s + 1));
+      const double bc2 = 1.0 - std::pow(o.adam_b2, (double)(s + 1));
+      for (int i = 0; i < P; ++i) {
+        const bool is_beta = i >= M + MM;
+        if (is_beta && o.fix_beta) continue;
+        const double gn = gv[i] * inv_n;
+        double step;
+        if (o.optimizer == 0) {
+          step = o.lr * gn;
+        } else {
+          m1[i] = o.adam_b1 * m1[i] + (1.0 - o.adam_b1) * gn;
+          m2[i] = o.adam_b2 * m2[i] + (1.0 - o.adam_b2) * gn * gn;
+          step = o.lr * (m1[i] / bc1) / (std::sqrt(m2[i] / bc2) + o.adam_eps);
+        }
+        double v = th[i] + step;
+        if (i < M) v = std::max(v, mu_min);
+        else if (!is_beta) v = std::max(v, 0.0);
+        else v = std::max(v, beta_min);
+        th[i] = v;
+      }
+    }
+    std::copy(th_eval.begin(), th_eval.begin() + M, mu + w * M);
+    std::copy(th_eval.begin() + M, th_eval.begin() + M + MM, alpha + w * MM);
+    if (beta_mode == 0) beta[w] = th_eval[M + MM];
+    else std::copy(th_eval.begin() + M + MM, th_eval.end(), beta + w * MM);
+    ll[w] = ll_eval;
+    steps[w] = s;
+    status[w] = st;
+  });
+  return 0;
+}
+
+// Tolerance scales (see Scale): ll_scale[W], s_mu[W*M], s_alpha[W*M*M],
+// s_beta[W] (shared mode: summed over pairs) or [W*M*M].
+int mdhp_oracle_scales(const int64_t* offsets, const double* t, const int32_t* dim,
+                       const double* T, int64_t W, int32_t M, int32_t beta_mode,
+                       const double* mu, const double* alpha, const double* beta,
+                       double* ll_scale, double* s_mu, double* s_alpha, double* s_beta,
+                       int32_t nthreads) {
+  if (beta_mode != 0 && beta_mode != 1) return -1;
+  if (!mu || !alpha || !beta || !ll_scale || !s_mu || !s_alpha || !s_beta) return -1;
+  int rc = check_batch(offsets, t, dim, T, W, M);
+  if (rc) return rc;
+  for_windows(W, nthreads, [&](int64_t w) {
+    Window win{t + offsets[w], dim + offsets[w], offsets[w + 1] - offsets[w], T[w]};
+    Params p = load_params(M, beta_mode, mu, alpha, beta, w);
+    Scale sc;
+    recursion_window(win, p, nullptr, &sc);
+    ll_scale[w] = sc.ll;
+    Grad g{sc.mu, sc.alpha, sc.beta};
+    store_grad(g, M, beta_mode, w, s_mu, s_alpha, s_beta);
+  });
+  return 0;
+}
+
+// Threads the pool uses when nthreads <= 0 is passed.
+int mdhp_oracle_default_threads(void) {
+  return (int)std::max(1u, std::thread::hardware_concurrency());
+}
+
+}  // extern "C"
