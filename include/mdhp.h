@@ -1,0 +1,166 @@
+/*
+ * mdhp.h - C ABI of the MI355X (gfx950) library that fits exponential-kernel
+ * multi-dimensional Hawkes process (MDHP) parameters over many event windows.
+ *
+ * The method is the MDHP gradient descent solver of "MDHP-Net" (Sec. IV-B):
+ * maximise the closed-form log-likelihood of Eq. (5) over (mu, alpha, beta),
+ * where Eq. (2) defines the conditional intensity
+ *     lambda_m(t) = mu_m + sum_n sum_{k: d_k = n, t_k < t} alpha_mn e^{-beta_mn (t - t_k)}
+ * and Eq. (5) (Part1 + Part2 + Part3, derived in Appendix B) is
+ *     ll = sum_i log lambda_{d_i}(t_i) - T sum_m mu_m
+ *          - sum_{m,n} alpha_mn / beta_mn sum_{k: d_k = n} (1 - e^{-beta_mn (T - t_k)}).
+ * The paper's theta is mu here, its D is M and its T_span is T.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Events: one merged, ragged CSR batch.  Window w owns events
+ *   [offsets[w], offsets[w+1]); t (FP64) is relative to the window start,
+ *   non-decreasing within the window, 0 <= t <= T[w]; dim (int32) is in
+ *   [0, M).  Events at equal times never excite each other (the sums of
+ *   Eq. (2) and Eq. (5) run over strictly earlier times), so the order
+ *   inside a group of equal times does not matter.
+ * Parameters (FP32, device memory, row-major):
+ *   mu[W][M]; alpha[W][M][M] with alpha[w][m][n] the excitation of target
+ *   m by source n (the direction the formula of Eq. (2) gives); beta[W]
+ *   (MDHP_BETA_SHARED: one decay per window) or beta[W][M][M]
+ *   (MDHP_BETA_PAIR: one decay per pair, the (D, D) beta of Sec. IV-B).
+ * Pointers: every array argument is DEVICE memory except mdhp_batch's
+ *   n_events/W scalars and the options struct, which are host values.  The
+ *   caller owns all buffers; the library allocates only in
+ *   mdhp_plan_create and frees in mdhp_plan_destroy; no other call
+ *   allocates.
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Compute
+ *   calls enqueue work and return; outputs are valid once the stream has
+ *   reached them.  A plan must not be used by two streams at once.
+ * Errors: every call returns an mdhp_status.  Structural input errors are
+ *   found synchronously in mdhp_plan_create.  Compute calls check their
+ *   arguments on the host (null pointers, a destroyed plan); they do not
+ *   read parameter values on the host, so invalid parameter values (mu <= 0,
+ *   alpha < 0, beta <= 0, non-finite) give non-finite results for the
+ *   affected windows instead of an error code; mdhp_fit_batch reports them
+ *   per window as MDHP_FIT_NONFINITE.  mdhp_last_error() returns a message
+ *   for the last failing call on the calling thread.
+ */
+#ifndef MDHP_H_
+#define MDHP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mdhp_status;
+enum {
+  MDHP_OK = 0,
+  MDHP_E_INVAL = -1,    /* null pointer, M outside [1, 64], W < 0, bad option */
+  MDHP_E_UNSORTED = -2, /* times decrease inside a window */
+  MDHP_E_DOMAIN = -3,   /* t < 0, t > T, dim outside [0, M), T <= 0 or not finite */
+  MDHP_E_PARAM = -4,    /* invalid parameter value (checked by the helpers below) */
+  MDHP_E_NOMEM = -5,    /* device allocation failed */
+  MDHP_E_HIP = -6       /* a HIP runtime call failed */
+};
+
+enum { MDHP_BETA_SHARED = 0, MDHP_BETA_PAIR = 1 };
+
+/* Update rules of mdhp_fit_batch (the paper optimises with an unnamed
+ * PyTorch optimizer; these are the rules this library offers). */
+enum { MDHP_OPT_PGD = 0, MDHP_OPT_PADAM = 1 };
+
+/* Per-window outcome of mdhp_fit_batch. */
+enum { MDHP_FIT_CONVERGED = 0, MDHP_FIT_MAX_STEPS = 1, MDHP_FIT_NONFINITE = 2 };
+
+/* Largest number of dimensions the kernels support. */
+#define MDHP_MAX_M 64
+
+typedef struct mdhp_batch {
+  int64_t W;              /* number of windows, >= 0 */
+  int64_t n_events;       /* offsets[W] (host value) */
+  const int64_t* offsets; /* device int64[W+1], offsets[0] == 0, non-decreasing */
+  const double* t;        /* device f64[n_events] */
+  const int32_t* dim;     /* device i32[n_events] */
+  const double* T;        /* device f64[W], window lengths, > 0 */
+} mdhp_batch;
+
+/* Options of mdhp_fit_batch.  Step s = 0, 1, ... evaluates ll_s and its
+ * gradient g_s at theta_s; the window stops as converged when s >= 1 and
+ * |ll_s - ll_{s-1}| <= ll_tol * max(|ll_s|, 1), stops as MAX_STEPS when
+ * s == max_steps, and otherwise moves to
+ *   theta_{s+1} = Proj(theta_s + step(g_s / max(N_w, 1)))
+ * with step = lr * g (PGD) or the bias-corrected Adam step (PADAM), and
+ * Proj clamping mu >= mu_floor_rel * r_w, alpha >= 0,
+ * beta >= beta_floor_rel * r_w, where r_w = max(N_w, 1) / T_w. */
+typedef struct mdhp_fit_opts {
+  int32_t max_steps; /* >= 0 */
+  int32_t optimizer; /* MDHP_OPT_PGD or MDHP_OPT_PADAM */
+  int32_t fix_beta;  /* non-zero: beta is not updated */
+  int32_t reserved;  /* must be 0 */
+  double lr;         /* > 0 */
+  double ll_tol;     /* >= 0 */
+  double mu_floor_rel;
+  double beta_floor_rel;
+  double adam_b1, adam_b2, adam_eps;
+} mdhp_fit_opts;
+
+typedef struct mdhp_plan mdhp_plan;
+
+/* Validates a batch and prepares it for the kernels (Sec. IV-B "Stage 1:
+ * Initialization" is the paper's counterpart).  Synchronous: runs the
+ * preparation kernel on `stream`, waits for it and returns
+ * MDHP_E_UNSORTED / MDHP_E_DOMAIN for bad events.  On success *out owns a
+ * compact copy of the events (FP32 gaps computed in FP64, u8 dims), the
+ * window order (largest first) and the workspace.  M in [1, 64];
+ * beta_mode MDHP_BETA_SHARED or MDHP_BETA_PAIR. */
+mdhp_status mdhp_plan_create(const mdhp_batch* batch, int32_t M, int32_t beta_mode, void* stream,
+                             mdhp_plan** out);
+
+/* Frees a plan (NULL is accepted).  Waits for the device to finish with it. */
+void mdhp_plan_destroy(mdhp_plan* plan);
+
+/* Number of windows / events / dimensions of a plan (0 for NULL). */
+int64_t mdhp_plan_windows(const mdhp_plan* plan);
+int64_t mdhp_plan_events(const mdhp_plan* plan);
+int32_t mdhp_plan_dims(const mdhp_plan* plan);
+
+/* Log-likelihood of Eq. (5) per window: ll[W] (device f64).  Part1 is
+ * evaluated by a segmented scan of the exponential-kernel recursion, Part2
+ * and Part3 in closed form from the scan's end state (Appendix B); per-window
+ * sums are reduced in FP64. */
+mdhp_status mdhp_loglik(mdhp_plan* plan, const float* mu, const float* alpha, const float* beta,
+                        double* ll, void* stream);
+
+/* Log-likelihood and its gradient (the ascent direction d ll / d theta, in
+ * the parameters' layouts): g_mu[W][M], g_alpha[W][M][M], g_beta[W] or
+ * [W][M][M] (device f32); ll[W] (device f64).  One pass per window; no
+ * backward scan. */
+mdhp_status mdhp_grad(mdhp_plan* plan, const float* mu, const float* alpha, const float* beta,
+                      double* ll, float* g_mu, float* g_alpha, float* g_beta, void* stream);
+
+/* Projected gradient fit of every window in one persistent launch.
+ * mu/alpha/beta hold the initial values on entry and the fitted values on
+ * return (theta_s of the last evaluation); ll[W] is ll at the returned
+ * parameters, steps[W] the number of updates applied, status[W] one of
+ * MDHP_FIT_*.  Non-finite windows keep their last finite parameters. */
+mdhp_status mdhp_fit_batch(mdhp_plan* plan, const mdhp_fit_opts* opts, float* mu, float* alpha,
+                           float* beta, double* ll, int32_t* steps, int32_t* status,
+                           void* stream);
+
+/* Checks parameter values on the device (mu > 0, alpha >= 0, beta > 0, all
+ * finite) and returns MDHP_E_PARAM if any window violates them.
+ * Synchronous on `stream`. */
+mdhp_status mdhp_check_params(mdhp_plan* plan, const float* mu, const float* alpha,
+                              const float* beta, void* stream);
+
+/* Static description of a status code. */
+const char* mdhp_status_string(mdhp_status status);
+
+/* Copies the calling thread's last error message into buf (NUL-terminated,
+ * truncated to n bytes) and returns the last error's status. */
+mdhp_status mdhp_last_error(char* buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDHP_H_ */

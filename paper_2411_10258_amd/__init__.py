@@ -1,0 +1,16 @@
+"""MI355X-native batched fitting of exponential-kernel multi-dimensional
+Hawkes processes (the estimation path of "MDHP-Net", Sec. IV-B).
+
+The computation lives in ``libmdhp.so`` (hand-written HIP for gfx950, C ABI
+in ``include/mdhp.h``); this package only marshals arguments.
+"""
+
+from .api import (BETA_PAIR, BETA_SHARED, FIT_CONVERGED, FIT_MAX_STEPS, FIT_NONFINITE,
+                  OPT_PADAM, OPT_PGD, FitOptions, MdhpError, Plan, mdhp_check_params,
+                  mdhp_fit_batch, mdhp_grad, mdhp_loglik, mdhp_plan_create, mdhp_plan_destroy,
+                  mdhp_status_string)
+
+__all__ = ["Plan", "FitOptions", "MdhpError", "mdhp_plan_create", "mdhp_plan_destroy",
+           "mdhp_loglik", "mdhp_grad", "mdhp_fit_batch", "mdhp_check_params",
+           "mdhp_status_string", "BETA_SHARED", "BETA_PAIR", "OPT_PGD", "OPT_PADAM",
+           "FIT_CONVERGED", "FIT_MAX_STEPS", "FIT_NONFINITE"]

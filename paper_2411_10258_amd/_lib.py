@@ -1,0 +1,94 @@
+"""ctypes loader for libmdhp.so (the HIP library's C ABI, include/mdhp.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels.  Importing this module does not need a GPU; loading the library
+does not either (symbols resolve against the HIP runtime), but every compute
+call does.  A missing library is an error, never a fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmdhp.so")
+
+# Every symbol include/mdhp.h declares.
+EXPORTS = (
+    "mdhp_plan_create", "mdhp_plan_destroy", "mdhp_plan_windows", "mdhp_plan_events",
+    "mdhp_plan_dims", "mdhp_loglik", "mdhp_grad", "mdhp_fit_batch", "mdhp_check_params",
+    "mdhp_status_string", "mdhp_last_error",
+)
+
+MDHP_OK = 0
+STATUS_NAMES = {0: "MDHP_OK", -1: "MDHP_E_INVAL", -2: "MDHP_E_UNSORTED", -3: "MDHP_E_DOMAIN",
+                -4: "MDHP_E_PARAM", -5: "MDHP_E_NOMEM", -6: "MDHP_E_HIP"}
+BETA_SHARED, BETA_PAIR = 0, 1
+OPT_PGD, OPT_PADAM = 0, 1
+FIT_CONVERGED, FIT_MAX_STEPS, FIT_NONFINITE = 0, 1, 2
+MAX_M = 64
+
+
+class MdhpBatch(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_int64), ("n_events", ctypes.c_int64),
+                ("offsets", ctypes.c_void_p), ("t", ctypes.c_void_p),
+                ("dim", ctypes.c_void_p), ("T", ctypes.c_void_p)]
+
+
+class MdhpFitOpts(ctypes.Structure):
+    _fields_ = [("max_steps", ctypes.c_int32), ("optimizer", ctypes.c_int32),
+                ("fix_beta", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("lr", ctypes.c_double), ("ll_tol", ctypes.c_double),
+                ("mu_floor_rel", ctypes.c_double), ("beta_floor_rel", ctypes.c_double),
+                ("adam_b1", ctypes.c_double), ("adam_b2", ctypes.c_double),
+                ("adam_eps", ctypes.c_double)]
+
+
+class MdhpError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads the in-tree libmdhp.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2411_10258_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.mdhp_plan_create.argtypes = [ctypes.POINTER(MdhpBatch), I32, I32, P, ctypes.POINTER(P)]
+    lib.mdhp_plan_destroy.argtypes = [P]
+    lib.mdhp_plan_destroy.restype = None
+    for name in ("mdhp_plan_windows", "mdhp_plan_events"):
+        getattr(lib, name).argtypes = [P]
+        getattr(lib, name).restype = I64
+    lib.mdhp_plan_dims.argtypes = [P]
+    lib.mdhp_plan_dims.restype = I32
+    lib.mdhp_loglik.argtypes = [P, P, P, P, P, P]
+    lib.mdhp_grad.argtypes = [P, P, P, P, P, P, P, P, P]
+    lib.mdhp_fit_batch.argtypes = [P, ctypes.POINTER(MdhpFitOpts), P, P, P, P, P, P, P]
+    lib.mdhp_check_params.argtypes = [P, P, P, P, P]
+    lib.mdhp_status_string.argtypes = [I32]
+    lib.mdhp_status_string.restype = ctypes.c_char_p
+    lib.mdhp_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    for name in ("mdhp_plan_create", "mdhp_loglik", "mdhp_grad", "mdhp_fit_batch",
+                 "mdhp_check_params", "mdhp_last_error"):
+        getattr(lib, name).restype = I32
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> None:
+    if status != MDHP_OK:
+        lib = load()
+        buf = ctypes.create_string_buffer(512)
+        lib.mdhp_last_error(buf, len(buf))
+        raise MdhpError(status, buf.value.decode(errors="replace"))

@@ -1,0 +1,180 @@
+"""Python binding of the C ABI, same names as include/mdhp.h.
+
+PyTorch supplies device memory and the current stream only: every array
+handed to the library is a contiguous HIP (``torch.cuda``) tensor, and the
+library's kernels do all of the arithmetic.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import (BETA_PAIR, BETA_SHARED, FIT_CONVERGED, FIT_MAX_STEPS, FIT_NONFINITE,
+                   OPT_PADAM, OPT_PGD, MdhpError)
+
+__all__ = ["Plan", "FitOptions", "mdhp_plan_create", "mdhp_plan_destroy", "mdhp_loglik",
+           "mdhp_grad", "mdhp_fit_batch", "mdhp_check_params", "mdhp_status_string",
+           "BETA_SHARED", "BETA_PAIR", "OPT_PGD", "OPT_PADAM", "FIT_CONVERGED",
+           "FIT_MAX_STEPS", "FIT_NONFINITE", "MdhpError"]
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev(x, dtype, device) -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        if x.device.type != "cuda":
+            x = x.to(device)
+        return x.to(dtype).contiguous()
+    return torch.as_tensor(x, dtype=dtype, device=device).contiguous()
+
+
+def _ptr(x: torch.Tensor):
+    return ctypes.c_void_p(x.data_ptr())
+
+
+@dataclass
+class FitOptions:
+    """Mirror of ``mdhp_fit_opts``."""
+    max_steps: int = 500
+    optimizer: int = OPT_PADAM
+    fix_beta: bool = False
+    lr: float = 1e-2
+    ll_tol: float = 1e-5
+    mu_floor_rel: float = 1e-6
+    beta_floor_rel: float = 1e-3
+    adam_b1: float = 0.9
+    adam_b2: float = 0.999
+    adam_eps: float = 1e-8
+
+    def to_c(self) -> _lib.MdhpFitOpts:
+        return _lib.MdhpFitOpts(int(self.max_steps), int(self.optimizer), int(bool(self.fix_beta)),
+                                0, float(self.lr), float(self.ll_tol), float(self.mu_floor_rel),
+                                float(self.beta_floor_rel), float(self.adam_b1),
+                                float(self.adam_b2), float(self.adam_eps))
+
+
+def mdhp_status_string(status: int) -> str:
+    return _lib.load().mdhp_status_string(int(status)).decode()
+
+
+def mdhp_plan_create(offsets, t, dim, T, M: int, beta_mode: int = BETA_SHARED,
+                     device="cuda", stream=None) -> int:
+    """Validates and prepares a batch; returns the raw plan handle."""
+    lib = _lib.load()
+    offsets = _dev(offsets, torch.int64, device)
+    t = _dev(t, torch.float64, device)
+    dim = _dev(dim, torch.int32, device)
+    T = _dev(T, torch.float64, device)
+    b = _lib.MdhpBatch(T.numel(), t.numel(), offsets.data_ptr(), t.data_ptr(), dim.data_ptr(),
+                       T.data_ptr())
+    h = ctypes.c_void_p()
+    _lib.check(lib.mdhp_plan_create(ctypes.byref(b), int(M), int(beta_mode),
+                                    ctypes.c_void_p(_stream(stream)), ctypes.byref(h)))
+    return h.value
+
+
+def mdhp_plan_destroy(handle: int) -> None:
+    if handle:
+        _lib.load().mdhp_plan_destroy(ctypes.c_void_p(handle))
+
+
+def mdhp_loglik(handle, mu, alpha, beta, ll, stream=None) -> None:
+    _lib.check(_lib.load().mdhp_loglik(ctypes.c_void_p(handle), _ptr(mu), _ptr(alpha), _ptr(beta),
+                                       _ptr(ll), ctypes.c_void_p(_stream(stream))))
+
+
+def mdhp_grad(handle, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, stream=None) -> None:
+    _lib.check(_lib.load().mdhp_grad(ctypes.c_void_p(handle), _ptr(mu), _ptr(alpha), _ptr(beta),
+                                     _ptr(ll), _ptr(g_mu), _ptr(g_alpha), _ptr(g_beta),
+                                     ctypes.c_void_p(_stream(stream))))
+
+
+def mdhp_fit_batch(handle, opts: FitOptions, mu, alpha, beta, ll, steps, status,
+                   stream=None) -> None:
+    c = opts.to_c()
+    _lib.check(_lib.load().mdhp_fit_batch(ctypes.c_void_p(handle), ctypes.byref(c), _ptr(mu),
+                                          _ptr(alpha), _ptr(beta), _ptr(ll), _ptr(steps),
+                                          _ptr(status), ctypes.c_void_p(_stream(stream))))
+
+
+def mdhp_check_params(handle, mu, alpha, beta, stream=None) -> None:
+    _lib.check(_lib.load().mdhp_check_params(ctypes.c_void_p(handle), _ptr(mu), _ptr(alpha),
+                                             _ptr(beta), ctypes.c_void_p(_stream(stream))))
+
+
+class Plan:
+    """A prepared batch of windows (owns a ``mdhp_plan``).
+
+    offsets int64[W+1], t float64[sum N], dim int32[sum N], T float64[W]
+    (host arrays or device tensors); M dimensions; beta_mode BETA_SHARED
+    (beta[W]) or BETA_PAIR (beta[W, M, M]).
+    """
+
+    def __init__(self, offsets, t, dim, T, M: int, beta_mode: int = BETA_SHARED,
+                 device="cuda", stream=None):
+        self.device = torch.device(device)
+        self.M = int(M)
+        self.beta_mode = int(beta_mode)
+        self.handle = None
+        self.handle = mdhp_plan_create(offsets, t, dim, T, M, beta_mode, device, stream)
+        lib = _lib.load()
+        self.W = int(lib.mdhp_plan_windows(ctypes.c_void_p(self.handle)))
+        self.n_events = int(lib.mdhp_plan_events(ctypes.c_void_p(self.handle)))
+
+    def close(self) -> None:
+        if self.handle:
+            mdhp_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _params(self, mu, alpha, beta):
+        W, M = self.W, self.M
+        mu = _dev(mu, torch.float32, self.device)
+        alpha = _dev(alpha, torch.float32, self.device)
+        beta = _dev(beta, torch.float32, self.device)
+        bshape = (W,) if self.beta_mode == BETA_SHARED else (W, M, M)
+        if mu.shape != (W, M) or alpha.shape != (W, M, M) or tuple(beta.shape) != bshape:
+            raise ValueError(f"parameter shapes {tuple(mu.shape)}, {tuple(alpha.shape)}, "
+                             f"{tuple(beta.shape)} do not match W={W}, M={M}")
+        return mu, alpha, beta
+
+    def loglik(self, mu, alpha, beta, stream=None) -> torch.Tensor:
+        mu, alpha, beta = self._params(mu, alpha, beta)
+        ll = torch.empty(self.W, dtype=torch.float64, device=self.device)
+        mdhp_loglik(self.handle, mu, alpha, beta, ll, stream)
+        return ll
+
+    def grad(self, mu, alpha, beta, stream=None):
+        mu, alpha, beta = self._params(mu, alpha, beta)
+        ll = torch.empty(self.W, dtype=torch.float64, device=self.device)
+        g_mu = torch.empty_like(mu)
+        g_alpha = torch.empty_like(alpha)
+        g_beta = torch.empty_like(beta)
+        mdhp_grad(self.handle, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, stream)
+        return ll, g_mu, g_alpha, g_beta
+
+    def fit(self, mu, alpha, beta, opts: FitOptions | None = None, stream=None):
+        """Fits every window; returns (mu, alpha, beta, ll, steps, status)."""
+        opts = opts or FitOptions()
+        mu, alpha, beta = (x.clone() for x in self._params(mu, alpha, beta))
+        ll = torch.empty(self.W, dtype=torch.float64, device=self.device)
+        steps = torch.empty(self.W, dtype=torch.int32, device=self.device)
+        status = torch.empty(self.W, dtype=torch.int32, device=self.device)
+        mdhp_fit_batch(self.handle, opts, mu, alpha, beta, ll, steps, status, stream)
+        return mu, alpha, beta, ll, steps, status
+
+    def check_params(self, mu, alpha, beta, stream=None) -> None:
+        mu, alpha, beta = self._params(mu, alpha, beta)
+        mdhp_check_params(self.handle, mu, alpha, beta, stream)

@@ -1,0 +1,328 @@
+// C ABI of libmdhp: plan creation (validation + compact preparation of the
+// events), the compute entry points and error reporting.
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "mdhp_internal.h"
+
+struct mdhp_plan {
+  int64_t W = 0, N = 0;
+  int32_t M = 0, beta_mode = 0;
+  float* dt = nullptr;
+  uint8_t* d = nullptr;
+  int64_t* begin = nullptr;
+  int32_t* n = nullptr;
+  double* T = nullptr;
+  float* end_gap = nullptr;
+  int32_t* order = nullptr;
+  int* counter = nullptr;  // window queue head
+  int* flags = nullptr;    // [0] error bits of prepare / check_params
+  uint32_t magic = 0;
+};
+
+namespace mdhp {
+
+__global__ void reset_counter_kernel(int* counter) { *counter = 0; }
+
+namespace {
+
+constexpr uint32_t kMagic = 0x4d444850u;  // "MDHP"
+constexpr int kErrUnsorted = 1, kErrDomain = 2, kErrParam = 4;
+
+thread_local std::string g_last_msg;
+thread_local mdhp_status g_last_status = MDHP_OK;
+
+mdhp_status fail(mdhp_status s, const std::string& msg) {
+  g_last_status = s;
+  g_last_msg = msg;
+  return s;
+}
+
+mdhp_status hip_fail(hipError_t e, const char* where) {
+  return fail(e == hipErrorOutOfMemory ? MDHP_E_NOMEM : MDHP_E_HIP,
+              std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Sec. IV-B "Stage 1" counterpart: per event, the gap to the previous event
+// of the same window in FP64 (stored FP32; a positive gap never rounds to 0),
+// the u8 dimension id, and validation of order and domain.
+__global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double* __restrict__ t,
+                               const int32_t* __restrict__ dim, const double* __restrict__ T,
+                               int64_t W, int M, float* __restrict__ dt,
+                               uint8_t* __restrict__ d8, float* __restrict__ end_gap,
+                               double* __restrict__ Tc, int* flags) {
+  for (int64_t w = blockIdx.x; w < W; w += gridDim.x) {
+    const int64_t b = offsets[w], e = offsets[w + 1];
+    const double Tw = T[w];
+    int err = 0;
+    if (!(Tw > 0.0) || !isfinite(Tw)) err |= kErrDomain;
+    for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+      const double ti = t[i];
+      const double prev = i > b ? t[i - 1] : 0.0;
+      if (!(ti >= 0.0) || !(ti <= Tw)) err |= kErrDomain;
+      if (i > b && ti < prev) err |= kErrUnsorted;
+      const int di = dim[i];
+      if (di < 0 || di >= M) err |= kErrDomain;
+      float g = (float)(ti - prev);
+      if (ti > prev && !(g > 0.f)) g = 1.17549435e-38f;
+      dt[i] = g > 0.f ? g : 0.f;
+      d8[i] = (uint8_t)(di < 0 ? 0 : (di >= M ? 0 : di));
+    }
+    if (threadIdx.x == 0) {
+      const double last = e > b ? t[e - 1] : 0.0;
+      float g = (float)(Tw - last);
+      end_gap[w] = g > 0.f ? g : 0.f;
+      Tc[w] = Tw;
+    }
+    if (err) atomicOr(flags, err);
+  }
+}
+
+// mu > 0, alpha >= 0, beta > 0, all finite.
+__global__ void check_params_kernel(const float* mu, const float* alpha, const float* beta,
+                                    int64_t n_mu, int64_t n_alpha, int64_t n_beta, int* flags) {
+  int bad = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_alpha; i += stride) {
+    if (i < n_mu && !(mu[i] > 0.f && isfinite(mu[i]))) bad = 1;
+    if (!(alpha[i] >= 0.f && isfinite(alpha[i]))) bad = 1;
+    if (i < n_beta && !(beta[i] > 0.f && isfinite(beta[i]))) bad = 1;
+  }
+  if (bad) atomicOr(flags, kErrParam);
+}
+
+__global__ void zero_int_kernel(int* p) { *p = 0; }
+
+bool plan_ok(const mdhp_plan* p) { return p && p->magic == kMagic; }
+
+Events events_of(const mdhp_plan* p) {
+  return Events{p->W, p->dt, p->d, p->begin, p->n, p->T, p->end_gap, p->order};
+}
+
+template <class T>
+hipError_t dev_alloc(T** ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)ptr, count * sizeof(T));
+}
+
+void free_plan(mdhp_plan* p) {
+  if (!p) return;
+  (void)hipFree(p->dt);
+  (void)hipFree(p->d);
+  (void)hipFree(p->begin);
+  (void)hipFree(p->n);
+  (void)hipFree(p->T);
+  (void)hipFree(p->end_gap);
+  (void)hipFree(p->order);
+  (void)hipFree(p->counter);
+  (void)hipFree(p->flags);
+  p->magic = 0;
+  delete p;
+}
+
+}  // namespace
+}  // namespace mdhp
+
+using namespace mdhp;
+
+extern "C" {
+
+const char* mdhp_status_string(mdhp_status s) {
+  switch (s) {
+    case MDHP_OK: return "ok";
+    case MDHP_E_INVAL: return "invalid argument";
+    case MDHP_E_UNSORTED: return "event times decrease inside a window";
+    case MDHP_E_DOMAIN: return "event time, dimension or window length out of range";
+    case MDHP_E_PARAM: return "invalid parameter value";
+    case MDHP_E_NOMEM: return "device allocation failed";
+    case MDHP_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+mdhp_status mdhp_last_error(char* buf, size_t n) {
+  if (buf && n) {
+    std::snprintf(buf, n, "%s", g_last_msg.c_str());
+  }
+  return g_last_status;
+}
+
+mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, void* stream,
+                             mdhp_plan** out) {
+  if (!out) return fail(MDHP_E_INVAL, "plan_create: out is NULL");
+  *out = nullptr;
+  if (!b) return fail(MDHP_E_INVAL, "plan_create: batch is NULL");
+  if (M < 1 || M > MDHP_MAX_M) return fail(MDHP_E_INVAL, "plan_create: M must be in [1, 64]");
+  if (beta_mode != MDHP_BETA_SHARED && beta_mode != MDHP_BETA_PAIR)
+    return fail(MDHP_E_INVAL, "plan_create: unknown beta_mode");
+  if (b->W < 0 || b->n_events < 0) return fail(MDHP_E_INVAL, "plan_create: negative sizes");
+  if (b->W > INT32_MAX) return fail(MDHP_E_INVAL, "plan_create: too many windows");
+  if (!b->offsets || (b->W > 0 && !b->T) || (b->n_events > 0 && (!b->t || !b->dim)))
+    return fail(MDHP_E_INVAL, "plan_create: null array");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t W = b->W;
+  std::vector<int64_t> off(W + 1);
+  hipError_t e = hipMemcpyAsync(off.data(), b->offsets, (W + 1) * sizeof(int64_t),
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "plan_create: reading offsets");
+  if (off[0] != 0) return fail(MDHP_E_INVAL, "plan_create: offsets[0] != 0");
+  for (int64_t w = 0; w < W; ++w) {
+    if (off[w + 1] < off[w]) return fail(MDHP_E_INVAL, "plan_create: offsets decrease");
+    if (off[w + 1] - off[w] > INT32_MAX)
+      return fail(MDHP_E_INVAL, "plan_create: window has more than 2^31-1 events");
+  }
+  if (off[W] != b->n_events) return fail(MDHP_E_INVAL, "plan_create: offsets[W] != n_events");
+
+  mdhp_plan* p = new mdhp_plan();
+  p->W = W;
+  p->N = b->n_events;
+  p->M = M;
+  p->beta_mode = beta_mode;
+  p->magic = kMagic;
+  const int64_t N = b->n_events;
+  if ((e = dev_alloc(&p->dt, N)) != hipSuccess || (e = dev_alloc(&p->d, N)) != hipSuccess ||
+      (e = dev_alloc(&p->begin, W)) != hipSuccess || (e = dev_alloc(&p->n, W)) != hipSuccess ||
+      (e = dev_alloc(&p->T, W)) != hipSuccess || (e = dev_alloc(&p->end_gap, W)) != hipSuccess ||
+      (e = dev_alloc(&p->order, W)) != hipSuccess ||
+      (e = dev_alloc(&p->counter, 1)) != hipSuccess ||
+      (e = dev_alloc(&p->flags, 1)) != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "plan_create: allocation");
+  }
+  // Window sizes and the largest-first order, on the host.
+  std::vector<int32_t> cnt(W), order(W);
+  for (int64_t w = 0; w < W; ++w) cnt[w] = (int32_t)(off[w + 1] - off[w]);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t c) { return cnt[a] > cnt[c]; });
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, p->flags);
+  e = hipGetLastError();
+  if (e == hipSuccess && W > 0) {
+    e = hipMemcpyAsync(p->begin, off.data(), W * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p->n, cnt.data(), W * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p->order, order.data(), W * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+      const int grid = (int)std::min<int64_t>(W, 65536);
+      hipLaunchKernelGGL(prepare_kernel, dim3(grid), dim3(256), 0, s, b->offsets, b->t, b->dim,
+                         b->T, W, M, p->dt, p->d, p->end_gap, p->T, p->flags);
+      e = hipGetLastError();
+    }
+  }
+  int flags = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&flags, p->flags, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "plan_create: prepare");
+  }
+  if (flags & kErrUnsorted) {
+    free_plan(p);
+    return fail(MDHP_E_UNSORTED, "plan_create: event times decrease inside a window");
+  }
+  if (flags & kErrDomain) {
+    free_plan(p);
+    return fail(MDHP_E_DOMAIN, "plan_create: t outside [0, T], dim outside [0, M) or bad T");
+  }
+  *out = p;
+  return MDHP_OK;
+}
+
+void mdhp_plan_destroy(mdhp_plan* p) {
+  if (!plan_ok(p)) return;
+  (void)hipDeviceSynchronize();
+  free_plan(p);
+}
+
+int64_t mdhp_plan_windows(const mdhp_plan* p) { return plan_ok(p) ? p->W : 0; }
+int64_t mdhp_plan_events(const mdhp_plan* p) { return plan_ok(p) ? p->N : 0; }
+int32_t mdhp_plan_dims(const mdhp_plan* p) { return plan_ok(p) ? p->M : 0; }
+
+mdhp_status mdhp_loglik(mdhp_plan* p, const float* mu, const float* alpha, const float* beta,
+                        double* ll, void* stream) {
+  if (!plan_ok(p)) return fail(MDHP_E_INVAL, "loglik: invalid plan");
+  if (p->W > 0 && (!mu || !alpha || !beta || !ll))
+    return fail(MDHP_E_INVAL, "loglik: null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  const Events ev = events_of(p);
+  hipError_t e = p->beta_mode == MDHP_BETA_SHARED
+                     ? shared_eval(ev, p->M, mu, alpha, beta, ll, nullptr, nullptr, nullptr,
+                                   p->counter, s, false)
+                     : pair_eval(ev, p->M, mu, alpha, beta, ll, nullptr, nullptr, nullptr,
+                                 p->counter, s, false);
+  if (e != hipSuccess) return hip_fail(e, "loglik: launch");
+  return MDHP_OK;
+}
+
+mdhp_status mdhp_grad(mdhp_plan* p, const float* mu, const float* alpha, const float* beta,
+                      double* ll, float* g_mu, float* g_alpha, float* g_beta, void* stream) {
+  if (!plan_ok(p)) return fail(MDHP_E_INVAL, "grad: invalid plan");
+  if (p->W > 0 && (!mu || !alpha || !beta || !ll || !g_mu || !g_alpha || !g_beta))
+    return fail(MDHP_E_INVAL, "grad: null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  const Events ev = events_of(p);
+  hipError_t e = p->beta_mode == MDHP_BETA_SHARED
+                     ? shared_eval(ev, p->M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta,
+                                   p->counter, s, true)
+                     : pair_eval(ev, p->M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta,
+                                 p->counter, s, true);
+  if (e != hipSuccess) return hip_fail(e, "grad: launch");
+  return MDHP_OK;
+}
+
+mdhp_status mdhp_fit_batch(mdhp_plan* p, const mdhp_fit_opts* o, float* mu, float* alpha,
+                           float* beta, double* ll, int32_t* steps, int32_t* status,
+                           void* stream) {
+  if (!plan_ok(p)) return fail(MDHP_E_INVAL, "fit_batch: invalid plan");
+  if (!o) return fail(MDHP_E_INVAL, "fit_batch: opts is NULL");
+  if (p->W > 0 && (!mu || !alpha || !beta || !ll || !steps || !status))
+    return fail(MDHP_E_INVAL, "fit_batch: null pointer");
+  if (o->max_steps < 0 || !(o->lr > 0.0) || !std::isfinite(o->lr) || !(o->ll_tol >= 0.0) ||
+      (o->optimizer != MDHP_OPT_PGD && o->optimizer != MDHP_OPT_PADAM) || o->reserved != 0 ||
+      !(o->mu_floor_rel >= 0.0) || !(o->beta_floor_rel >= 0.0) ||
+      (o->optimizer == MDHP_OPT_PADAM &&
+       !(o->adam_b1 >= 0.0 && o->adam_b1 < 1.0 && o->adam_b2 >= 0.0 && o->adam_b2 < 1.0 &&
+         o->adam_eps >= 0.0)))
+    return fail(MDHP_E_INVAL, "fit_batch: invalid options");
+  FitParams fp{o->max_steps, o->optimizer, o->fix_beta,  o->lr,      o->ll_tol,
+               o->mu_floor_rel, o->beta_floor_rel, o->adam_b1, o->adam_b2, o->adam_eps};
+  hipStream_t s = (hipStream_t)stream;
+  const Events ev = events_of(p);
+  hipError_t e = p->beta_mode == MDHP_BETA_SHARED
+                     ? shared_fit(ev, p->M, fp, mu, alpha, beta, ll, steps, status, p->counter, s)
+                     : pair_fit(ev, p->M, fp, mu, alpha, beta, ll, steps, status, p->counter, s);
+  if (e != hipSuccess) return hip_fail(e, "fit_batch: launch");
+  return MDHP_OK;
+}
+
+mdhp_status mdhp_check_params(mdhp_plan* p, const float* mu, const float* alpha,
+                              const float* beta, void* stream) {
+  if (!plan_ok(p)) return fail(MDHP_E_INVAL, "check_params: invalid plan");
+  if (p->W == 0) return MDHP_OK;
+  if (!mu || !alpha || !beta) return fail(MDHP_E_INVAL, "check_params: null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nm = p->W * p->M, na = p->W * p->M * p->M;
+  const int64_t nb = p->beta_mode == MDHP_BETA_SHARED ? p->W : na;
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, p->flags);
+  const int grid = (int)std::min<int64_t>((na + 255) / 256, 4096);
+  hipLaunchKernelGGL(check_params_kernel, dim3(grid), dim3(256), 0, s, mu, alpha, beta, nm, na,
+                     nb, p->flags);
+  int flags = 0;
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&flags, p->flags, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "check_params");
+  if (flags & kErrParam)
+    return fail(MDHP_E_PARAM, "check_params: mu <= 0, alpha < 0, beta <= 0 or non-finite");
+  return MDHP_OK;
+}
+
+}  // extern "C"
