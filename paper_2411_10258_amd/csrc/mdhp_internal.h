@@ -11,7 +11,6 @@
 namespace mdhp {
 
 constexpr int kBlock = 256;  // threads per workgroup (4 waves of 64)
-constexpr int kTile = 1024;  // events staged in LDS per tile
 
 // FP64 G_R accumulators each thread owns for a P x P matrix.
 constexpr int own_count(int P) { return P * P >= kBlock ? P * P / kBlock : 1; }

@@ -11,11 +11,13 @@
 // P counts the events that share the previous time (they are folded in only
 // when time moves on, so equal times never excite each other).
 //
-// Events are staged in LDS in tiles of kTile.  A tile is cut into one chunk
-// per group; the chunks' affine carries (product of decays, summed gaps, and
-// the zero-start end state) are combined in order by one group (the scan of
-// the (a, delta, b_R, b_S) monoid), then every group re-runs its chunk from
-// its exact start state and accumulates, per event i with target m = d_i:
+// Each group owns one contiguous chunk of the window (N / G events).  Pass 1
+// computes every chunk's affine carry from a zero start, one event per lane
+// (suffix sums of the gaps, one exponential per event, LDS atomics into the
+// chunk's state); one group combines the carries in order (the scan of the
+// (a, delta, b_R, b_S) monoid); pass 2 re-runs every chunk from its exact
+// start state in batches of B events and accumulates, per event i with
+// target m = d_i:
 //   lambda_i = mu_m + sum_n alpha_mn R_n(i)          (Eq. (2) at t_i)
 //   ll      += log lambda_i                          (Part1)
 //   G_R[m][n] += R_n(i) / lambda_i                   (d ll / d alpha, Part1 share)
@@ -24,7 +26,9 @@
 // The compensator (Part2 + Part3, Appendix B) needs
 //   E_n = sum_{k: d_k = n} e^{-beta (T - t_k)},  F_n = sum (T - t_k) e^{-beta (T - t_k)},
 // which are the scan state advanced from the last event to T.
-// Per-chunk FP32 partial sums are folded into FP64 once per tile.
+// Per-lane FP32 partial sums are reduced in FP64 at the end of the window.
+
+#include <utility>
 
 #include "mdhp_internal.h"
 
@@ -50,6 +54,47 @@ __device__ __forceinline__ float group_sum(float v) {
   return v;
 }
 
+// Lane J of the caller's group, broadcast to the whole group (J < P).
+template <int P, int J>
+__device__ __forceinline__ float group_bcast(float x) {
+  const int v = __builtin_bit_cast(int, x);
+  int r;
+  if constexpr (P == 4) r = __builtin_amdgcn_mov_dpp(v, J * 0x55, 0xF, 0xF, false);  // quad_perm [J,J,J,J]
+  else if constexpr (P == 8) r = __builtin_amdgcn_ds_swizzle(v, 0x18 | (J << 5));      // (lane & 24) | J
+  else if constexpr (P == 16) r = __builtin_amdgcn_mov_dpp(v, 0x150 + J, 0xF, 0xF, false);  // row_newbcast
+  else if constexpr (P == 32) r = __builtin_amdgcn_ds_swizzle(v, J << 5);              // lane J of the 32
+  else r = __builtin_amdgcn_readlane(v, J);
+  return __builtin_bit_cast(float, r);
+}
+
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+
+// f(std::integral_constant<int, j>) for j = 0 .. N-1, fully unrolled.
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Inclusive prefix sum over the P lanes of a group (lane order).
+template <int P>
+__device__ __forceinline__ float group_scan(float v, int lane) {
+#pragma unroll
+  for (int k = 1; k < P; k <<= 1) {
+    const float y = __shfl_up(v, k, P);
+    if (lane >= k) v += y;
+  }
+  return v;
+}
+
+#ifndef MDHP_BATCH
+#define MDHP_BATCH 16
+#endif
+// Events per pass-2 batch (at most the group size).
+constexpr int kBatch = MDHP_BATCH;
+
 template <int P>
 struct SharedLds {
   static constexpr int G = kBlock / P;                 // groups (chunks) per tile
@@ -57,8 +102,6 @@ struct SharedLds {
   float alpha[P * P];  // alpha[m * P + n], zero outside M x M
   float mu[P];         // zero outside M
   float colsum[P];     // sum_m alpha_mn
-  float dt[kTile];
-  uint8_t d[kTile];
   float cR[G][P], cS[G][P], cP[G][P];  // chunk carries, then chunk start states
   float cA[G], cD[G];
   int cF[G];
@@ -84,136 +127,176 @@ __device__ void eval_window(SharedLds<P>& sh, const float* __restrict__ dtg,
                             float end_gap, int M, double (&gR64)[own_count(P)]) {
   constexpr int G = SharedLds<P>::G;
   constexpr int OWN = own_count(P);
+  constexpr int B = kBatch < P ? kBatch : P;
   const int tid = threadIdx.x;
   const int lane = tid & (P - 1);
   const int grp = tid / P;
   float* gRc = sh.gR[SharedLds<P>::NCOPY > 1 ? (tid >> 6) : 0];
   const float beta = sh.beta;
+  const float* __restrict__ dtw = dtg + begin;
+  const uint8_t* __restrict__ dw = dg + begin;
 
   double ll64 = 0.0, gmu64 = 0.0, gb64 = 0.0;
   int cnt = 0;
-#pragma unroll
-  for (int k = 0; k < OWN; ++k) gR64[k] = 0.0;
-  if (tid < P) {
-    sh.tR[tid] = 0.f;
-    sh.tS[tid] = 0.f;
-    sh.tP[tid] = 0.f;
-  }
+  // Group g owns the contiguous chunk [j0, j1) of the window.
+  const int c = (n + G - 1) / G;
+  const int j0 = min(grp * c, n);
+  const int len = min(j0 + c, n) - j0;
 
-  for (int base = 0; base < n; base += kTile) {
-    const int nt = min(kTile, n - base);
-    __syncthreads();
-    for (int i = tid; i < nt; i += kBlock) {
-      sh.dt[i] = dtg[begin + base + i];
-      sh.d[i] = dg[begin + base + i];
-    }
-    __syncthreads();
-    const int c = (nt + G - 1) / G;
-    const int j0 = grp * c;
-    const int j1 = min(j0 + c, nt);
-
-    // Pass 1: carry of this group's chunk from a zero start.
-    {
-      float R = 0.f, S = 0.f, Pn = 0.f, A = 1.f, D = 0.f;
-      int F = 0;
-      for (int jj = 0; jj < c; ++jj) {
-        const int j = j0 + jj;
-        const bool valid = j < j1;
-        const float dt = valid ? sh.dt[j] : 0.f;
-        const int d = valid ? (int)sh.d[j] : -1;
-        const bool f = dt > 0.f;
-        const float a = __expf(-beta * dt);
-        const float X = f ? R + Pn : R;
-        R = a * X;
-        S = fmaf(a, S, dt * R);
-        Pn = f ? 0.f : Pn;
-        Pn += (d == lane) ? 1.f : 0.f;
-        A *= a;
-        D += dt;
-        F |= f ? 1 : 0;
+  // Pass 1: carry of this group's chunk from a zero start, one event per
+  // lane.  An event at suffix time tau (sum of the later gaps of the chunk)
+  // adds e^{-beta tau} to R and tau e^{-beta tau} to S of its dimension, or
+  // counts as pending if no positive gap follows it (tau == 0); the chunk
+  // decays everything before it by e^{-beta delta}, delta = sum of its gaps.
+  {
+    sh.cR[grp][lane] = 0.f;
+    sh.cS[grp][lane] = 0.f;
+    sh.cP[grp][lane] = 0.f;
+    float later = 0.f;
+    const int nsub = (c + P - 1) / P;
+    int jr = (nsub - 1) * P + (P - 1 - lane);  // lanes run backwards through a sub-batch
+    float dt_n = jr < len ? dtw[j0 + jr] : 0.f;
+    int d_n = jr < len ? (int)dw[j0 + jr] : 0;
+    for (int bb = nsub - 1; bb >= 0; --bb) {
+      const bool valid = jr < len;
+      const float dt = dt_n;
+      const int d = d_n;
+      jr -= P;
+      if (bb > 0) {  // prefetch the previous sub-batch
+        dt_n = jr < len ? dtw[j0 + jr] : 0.f;
+        d_n = jr < len ? (int)dw[j0 + jr] : 0;
       }
-      sh.cR[grp][lane] = R;
-      sh.cS[grp][lane] = S;
-      sh.cP[grp][lane] = Pn;
-      if (lane == 0) {
-        sh.cA[grp] = A;
-        sh.cD[grp] = D;
-        sh.cF[grp] = F;
-      }
-    }
-    __syncthreads();
-    // Ordered combine of the chunk carries: chunk g starts from the state
-    // after chunks 0..g-1 (and the previous tiles).
-    if (grp == 0) {
-      float R = sh.tR[lane], S = sh.tS[lane], Pn = sh.tP[lane];
-      for (int g = 0; g < G; ++g) {
-        const float Rg = sh.cR[g][lane], Sg = sh.cS[g][lane], Pg = sh.cP[g][lane];
-        const float Ag = sh.cA[g], Dg = sh.cD[g];
-        const int Fg = sh.cF[g];
-        sh.cR[g][lane] = R;
-        sh.cS[g][lane] = S;
-        sh.cP[g][lane] = Pn;
-        if (Fg) {
-          const float X = R + Pn;
-          R = fmaf(Ag, X, Rg);
-          S = fmaf(Ag, fmaf(Dg, X, S), Sg);
-          Pn = Pg;
+      float prev = __shfl_up(dt, 1, P);  // gap of the next event (exclusive scan input)
+      prev = lane == 0 ? 0.f : prev;
+      const float tau = later + group_scan<P>(prev, lane);
+      if (valid) {
+        if (tau > 0.f) {
+          const float e = __expf(-beta * tau);
+          atomicAdd(&sh.cR[grp][d], e);
+          atomicAdd(&sh.cS[grp][d], tau * e);
         } else {
-          Pn += Pg;
+          atomicAdd(&sh.cP[grp][d], 1.f);
         }
       }
-      sh.tR[lane] = R;
-      sh.tS[lane] = S;
-      sh.tP[lane] = Pn;
+      later += group_sum<P>(dt);
     }
-    __syncthreads();
-    // Pass 2: exact states, intensities and gradient sums.
-    {
-      float R = sh.cR[grp][lane], S = sh.cS[grp][lane], Pn = sh.cP[grp][lane];
-      float llp = 0.f, gmup = 0.f, gbp = 0.f;
-      for (int jj = 0; jj < c; ++jj) {
-        const int j = j0 + jj;
-        const bool valid = j < j1;
-        const float dt = valid ? sh.dt[j] : 0.f;
-        const int d = valid ? (int)sh.d[j] : 0;
+    if (lane == 0) {
+      sh.cA[grp] = __expf(-beta * later);
+      sh.cD[grp] = later;
+      sh.cF[grp] = later > 0.f ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  // Ordered combine of the chunk carries: chunk g starts from the state
+  // after chunks 0..g-1; the final state is the window's end state.
+  if (grp == 0) {
+    float R = 0.f, S = 0.f, Pn = 0.f;
+    for (int g = 0; g < G; ++g) {
+      const float Rg = sh.cR[g][lane], Sg = sh.cS[g][lane], Pg = sh.cP[g][lane];
+      const float Ag = sh.cA[g], Dg = sh.cD[g];
+      const int Fg = sh.cF[g];
+      sh.cR[g][lane] = R;
+      sh.cS[g][lane] = S;
+      sh.cP[g][lane] = Pn;
+      if (Fg) {
+        const float X = R + Pn;
+        R = fmaf(Ag, X, Rg);
+        S = fmaf(Ag, fmaf(Dg, X, S), Sg);
+        Pn = Pg;
+      } else {
+        Pn += Pg;
+      }
+    }
+    sh.tR[lane] = R;
+    sh.tS[lane] = S;
+    sh.tP[lane] = Pn;
+  }
+  __syncthreads();
+  // Pass 2: exact states, intensities and gradient sums, B events per
+  // batch: the recurrence runs over the batch with the gaps, decays and
+  // dims broadcast from the lane that loaded them, the B intensity sums are
+  // independent group reductions, and lane j takes log and reciprocal of
+  // lambda_j for the whole group.
+  {
+    float R = sh.cR[grp][lane], S = sh.cS[grp][lane], Pn = sh.cP[grp][lane];
+    float llp = 0.f, gmup = 0.f, gbp = 0.f;
+    const int nb = (c + B - 1) / B;
+    int jl = lane & (B - 1);
+    float dt_n = jl < len ? dtw[j0 + jl] : 0.f;
+    int d_n = jl < len ? (int)dw[j0 + jl] : 0;
+    for (int bb = 0; bb < nb; ++bb) {
+      const bool vl = jl < len;
+      const float dt_l = dt_n;
+      const float d_l = __builtin_bit_cast(float, d_n);
+      const int nvalid = min(B, len - bb * B);  // valid events of this batch (may be <= 0)
+      jl += B;
+      if (bb + 1 < nb) {  // prefetch the next batch
+        dt_n = jl < len ? dtw[j0 + jl] : 0.f;
+        d_n = jl < len ? (int)dw[j0 + jl] : 0;
+      }
+      const float a_l = __expf(-beta * dt_l);
+      float Rj[B], Sj[B], Lj[B];
+      int Dj[B];
+      static_for<B>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        const float dt = group_bcast<P, j>(dt_l);
+        const float a = group_bcast<P, j>(a_l);
+        const int d = __builtin_bit_cast(int, group_bcast<P, j>(d_l));
         const bool f = dt > 0.f;
-        const float a = __expf(-beta * dt);
         const float X = f ? R + Pn : R;
         R = a * X;
         S = fmaf(a, S, dt * R);
         Pn = f ? 0.f : Pn;
-        const float al = sh.alpha[d * P + lane];
-        const float lam = group_sum<P>(al * R) + sh.mu[d];
-        const float lg = __logf(lam);
-        llp += (valid && lane == 0) ? lg : 0.f;
-        if constexpr (GRAD) {
-          const float w = valid ? __builtin_amdgcn_rcpf(lam) : 0.f;
-          gmup += (valid && d == lane) ? w : 0.f;
-          gbp = fmaf(w * al, S, gbp);
-          if (valid) atomicAdd(&gRc[d * P + lane], w * R);
-        }
-        const bool mine = valid && d == lane;
+        Rj[j] = R;
+        Sj[j] = S;
+        Dj[j] = d;
+        Lj[j] = sh.alpha[d * P + lane] * R;
+        const bool mine = j < nvalid && d == lane;
         Pn += mine ? 1.f : 0.f;
         cnt += mine ? 1 : 0;
+      });
+      static_for<B>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        Lj[j] = group_sum<P>(Lj[j]);
+      });
+      float lk = Lj[0];
+      static_for<B>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        if (j > 0) lk = (lane & (B - 1)) == j ? Lj[j] : lk;
+      });
+      lk += sh.mu[__builtin_bit_cast(int, d_l)];
+      const float lg = __logf(lk);
+      llp += (vl && lane < B) ? lg : 0.f;
+      if constexpr (GRAD) {
+        const float wk = vl ? __builtin_amdgcn_rcpf(lk) : 0.f;
+        static_for<B>([&](auto J) {
+          constexpr int j = decltype(J)::value;
+          const float w = group_bcast<P, j>(wk);  // zero for events past the chunk end
+          atomicAdd(&gRc[Dj[j] * P + lane], w * Rj[j]);
+          gbp = fmaf(w * sh.alpha[Dj[j] * P + lane], Sj[j], gbp);
+          gmup += Dj[j] == lane ? w : 0.f;
+        });
       }
-      ll64 += (double)llp;
-      gmu64 += (double)gmup;
-      gb64 += (double)gbp;
     }
-    if constexpr (GRAD) {
-      __syncthreads();
+    ll64 += (double)llp;
+    gmu64 += (double)gmup;
+    gb64 += (double)gbp;
+  }
 #pragma unroll
-      for (int k = 0; k < OWN; ++k) {
-        const int e = tid + k * kBlock;
-        if (e < P * P) {
-          float s = 0.f;
+  for (int k = 0; k < OWN; ++k) gR64[k] = 0.0;
+  if constexpr (GRAD) {
+    __syncthreads();
 #pragma unroll
-          for (int cpy = 0; cpy < SharedLds<P>::NCOPY; ++cpy) {
-            s += sh.gR[cpy][e];
-            sh.gR[cpy][e] = 0.f;
-          }
-          gR64[k] += (double)s;
+    for (int k = 0; k < OWN; ++k) {
+      const int e = tid + k * kBlock;
+      if (e < P * P) {
+        float sum = 0.f;
+#pragma unroll
+        for (int cpy = 0; cpy < SharedLds<P>::NCOPY; ++cpy) {
+          sum += sh.gR[cpy][e];
+          sh.gR[cpy][e] = 0.f;
         }
+        gR64[k] = (double)sum;
       }
     }
   }
