@@ -54,7 +54,7 @@ extern "C" {
 typedef int32_t mdhp_status;
 enum {
   MDHP_OK = 0,
-  MDHP_E_INVAL = -1,    /* null pointer, M outside [1, 64], W < 0, bad option */
+  MDHP_E_INVAL = -1,    /* null pointer, M outside [1, 64] ([1, 32] per pair), W < 0, bad option */
   MDHP_E_UNSORTED = -2, /* times decrease inside a window */
   MDHP_E_DOMAIN = -3,   /* t < 0, t > T, dim outside [0, M), T <= 0 or not finite */
   MDHP_E_PARAM = -4,    /* invalid parameter value (checked by the helpers below) */
@@ -65,14 +65,26 @@ enum {
 enum { MDHP_BETA_SHARED = 0, MDHP_BETA_PAIR = 1 };
 
 /* Update rules of mdhp_fit_batch (the paper optimises with an unnamed
- * PyTorch optimizer; these are the rules this library offers). */
-enum { MDHP_OPT_PGD = 0, MDHP_OPT_PADAM = 1 };
+ * PyTorch optimizer; these are the rules this library offers).
+ * MDHP_OPT_LBFGS is available with one decay per window. */
+enum { MDHP_OPT_PGD = 0, MDHP_OPT_PADAM = 1, MDHP_OPT_LBFGS = 2 };
 
-/* Per-window outcome of mdhp_fit_batch. */
-enum { MDHP_FIT_CONVERGED = 0, MDHP_FIT_MAX_STEPS = 1, MDHP_FIT_NONFINITE = 2 };
+/* Per-window outcome of mdhp_fit_batch.  STALLED: the L-BFGS line search
+ * accepted no step (the likelihood no longer increases measurably). */
+enum {
+  MDHP_FIT_CONVERGED = 0,
+  MDHP_FIT_MAX_STEPS = 1,
+  MDHP_FIT_NONFINITE = 2,
+  MDHP_FIT_STALLED = 3
+};
 
-/* Largest number of dimensions the kernels support. */
+/* Largest L-BFGS memory. */
+#define MDHP_MAX_HISTORY 16
+
+/* Largest number of dimensions the kernels support (one decay per window /
+ * one decay per pair). */
 #define MDHP_MAX_M 64
+#define MDHP_MAX_M_PAIR 32
 
 typedef struct mdhp_batch {
   int64_t W;              /* number of windows, >= 0 */
@@ -83,20 +95,35 @@ typedef struct mdhp_batch {
   const double* T;        /* device f64[W], window lengths, > 0 */
 } mdhp_batch;
 
-/* Options of mdhp_fit_batch.  Step s = 0, 1, ... evaluates ll_s and its
- * gradient g_s at theta_s; the window stops as converged when s >= 1 and
+/* Options of mdhp_fit_batch.  All rules work on f = -ll / max(N_w, 1) with
+ * the projection Proj: mu >= mu_floor_rel * r_w, alpha >= 0,
+ * beta >= beta_floor_rel * r_w, where r_w = max(N_w, 1) / T_w.
+ *
+ * PGD / PADAM: step s = 0, 1, ... evaluates ll_s and its gradient g_s at
+ * theta_s; the window stops as converged when s >= 1 and
  * |ll_s - ll_{s-1}| <= ll_tol * max(|ll_s|, 1), stops as MAX_STEPS when
  * s == max_steps, and otherwise moves to
  *   theta_{s+1} = Proj(theta_s + step(g_s / max(N_w, 1)))
- * with step = lr * g (PGD) or the bias-corrected Adam step (PADAM), and
- * Proj clamping mu >= mu_floor_rel * r_w, alpha >= 0,
- * beta >= beta_floor_rel * r_w, where r_w = max(N_w, 1) / T_w. */
+ * with step = lr * g (PGD) or the bias-corrected Adam step (PADAM).
+ *
+ * LBFGS (projected L-BFGS): per iteration, parameters at their bound whose
+ * gradient pushes outward are held fixed; the direction is the two-loop
+ * recursion over the last `history` (s, y) pairs applied to the free
+ * gradient of f, scaled by s.y / y.y of the newest pair (0.01 / max|g|
+ * without history), replaced by that scaled steepest-descent direction if
+ * it does not descend; the step is the first of t = 1, 1/2, ... (at most 20
+ * trials, each a likelihood + gradient evaluation) whose projected point
+ * satisfies f(x') <= f(x) + 1e-4 g.(x' - x); a pair enters the history if
+ * s.y > 1e-10 |s| |y|.  The window stops as converged when an accepted step
+ * changes ll by at most ll_tol * max(|ll|, 1) or the free gradient is zero,
+ * as MAX_STEPS after max_steps accepted steps, and as STALLED when no trial
+ * is accepted.  lr, adam_* are not used. */
 typedef struct mdhp_fit_opts {
   int32_t max_steps; /* >= 0 */
-  int32_t optimizer; /* MDHP_OPT_PGD or MDHP_OPT_PADAM */
+  int32_t optimizer; /* MDHP_OPT_PGD, MDHP_OPT_PADAM or MDHP_OPT_LBFGS */
   int32_t fix_beta;  /* non-zero: beta is not updated */
-  int32_t reserved;  /* must be 0 */
-  double lr;         /* > 0 */
+  int32_t history;   /* L-BFGS memory, 0 (= 8) .. MDHP_MAX_HISTORY */
+  double lr;         /* > 0 (PGD, PADAM) */
   double ll_tol;     /* >= 0 */
   double mu_floor_rel;
   double beta_floor_rel;
@@ -110,8 +137,8 @@ typedef struct mdhp_plan mdhp_plan;
  * preparation kernel on `stream`, waits for it and returns
  * MDHP_E_UNSORTED / MDHP_E_DOMAIN for bad events.  On success *out owns a
  * compact copy of the events (FP32 gaps computed in FP64, u8 dims), the
- * window order (largest first) and the workspace.  M in [1, 64];
- * beta_mode MDHP_BETA_SHARED or MDHP_BETA_PAIR. */
+ * window order (largest first) and the workspace.  M in [1, 64] with
+ * MDHP_BETA_SHARED, [1, 32] with MDHP_BETA_PAIR. */
 mdhp_status mdhp_plan_create(const mdhp_batch* batch, int32_t M, int32_t beta_mode, void* stream,
                              mdhp_plan** out);
 
@@ -137,20 +164,96 @@ mdhp_status mdhp_loglik(mdhp_plan* plan, const float* mu, const float* alpha, co
 mdhp_status mdhp_grad(mdhp_plan* plan, const float* mu, const float* alpha, const float* beta,
                       double* ll, float* g_mu, float* g_alpha, float* g_beta, void* stream);
 
-/* Projected gradient fit of every window in one persistent launch.
- * mu/alpha/beta hold the initial values on entry and the fitted values on
- * return (theta_s of the last evaluation); ll[W] is ll at the returned
- * parameters, steps[W] the number of updates applied, status[W] one of
- * MDHP_FIT_*.  Non-finite windows keep their last finite parameters. */
+/* Fit of every window in one persistent launch (windows largest first from
+ * an atomic queue; the whole iteration loop of a window runs inside one
+ * workgroup).  mu/alpha/beta hold the initial values on entry and the
+ * fitted values on return; ll[W] is ll at the returned parameters,
+ * steps[W] the number of updates applied, status[W] one of MDHP_FIT_*,
+ * and evals[W] (optional, may be NULL) the number of likelihood + gradient
+ * evaluations.  A window whose evaluation is not finite returns the
+ * parameters of that evaluation with status MDHP_FIT_NONFINITE. */
 mdhp_status mdhp_fit_batch(mdhp_plan* plan, const mdhp_fit_opts* opts, float* mu, float* alpha,
                            float* beta, double* ll, int32_t* steps, int32_t* status,
-                           void* stream);
+                           int32_t* evals, void* stream);
 
 /* Checks parameter values on the device (mu > 0, alpha >= 0, beta > 0, all
  * finite) and returns MDHP_E_PARAM if any window violates them.
  * Synchronous on `stream`. */
 mdhp_status mdhp_check_params(mdhp_plan* plan, const float* mu, const float* alpha,
                               const float* beta, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start (an addition around the paper's solver, which fits
+ * every window from scratch): count-histogram features, a 3-layer ReLU MLP
+ * trained on the GPU with BF16 MFMA GEMMs (FP32 accumulation and master
+ * weights, Adam), and the epilogue that turns its prediction into initial
+ * parameters with the cold start as fallback.
+ * ------------------------------------------------------------------------ */
+
+/* Features of every window of a batch (device pointers as in mdhp_batch):
+ * x[w][m * bins + b] = log1p(count_{m,b} * bins / T_w) as BF16 (uint16 bit
+ * patterns), where event (t, m) falls in bin floor(t * bins / T_w) (FP64,
+ * clamped to bins - 1).  x is device memory [W][M * bins]; M * bins <= 16384. */
+mdhp_status mdhp_features(const mdhp_batch* batch, int32_t M, int32_t bins, uint16_t* x,
+                          void* stream);
+
+typedef struct mdhp_surrogate mdhp_surrogate;
+
+/* MLP in_dim -> hidden -> hidden -> out_dim with ReLU after the two hidden
+ * layers; He-uniform weights from SplitMix64(seed), zero biases.  Allocates
+ * weights, Adam state and activations for batches of up to max_batch rows.
+ * Synchronous.  Parameters are one FP32 buffer: W1[hidden][in], b1[hidden],
+ * W2[hidden][hidden], b2[hidden], W3[out][hidden], b3[out]. */
+mdhp_status mdhp_surrogate_create(int32_t in_dim, int32_t hidden, int32_t out_dim,
+                                  int32_t max_batch, uint64_t seed, mdhp_surrogate** out);
+void mdhp_surrogate_destroy(mdhp_surrogate* s);
+
+/* Number of FP32 parameters; copies of them to / from a caller buffer
+ * (device memory, n_params floats).  set_weights also refreshes the BF16
+ * copies the GEMMs read.  Enqueued on stream. */
+int64_t mdhp_surrogate_num_params(const mdhp_surrogate* s);
+mdhp_status mdhp_surrogate_get_weights(mdhp_surrogate* s, float* dst, void* stream);
+mdhp_status mdhp_surrogate_set_weights(mdhp_surrogate* s, const float* src, void* stream);
+
+/* y[B][out_dim] (device f32) = MLP(x[B][in_dim] BF16).  B <= max_batch. */
+mdhp_status mdhp_surrogate_forward(mdhp_surrogate* s, const uint16_t* x, int32_t B, float* y,
+                                   void* stream);
+
+/* Copies the last forward pass's BF16 hidden activations (first B rows of
+ * each hidden layer, [B][hidden]) to caller device buffers. */
+mdhp_status mdhp_surrogate_get_hidden(mdhp_surrogate* s, int32_t B, uint16_t* h1, uint16_t* h2,
+                                      void* stream);
+
+/* Forward pass, mean squared error against target[B][out_dim] (device f32)
+ * into *loss (device f64), and the gradient of that loss with respect to
+ * every parameter (same layout as the weights), kept inside the surrogate;
+ * get_gradients copies them to a caller device buffer. */
+mdhp_status mdhp_surrogate_backward(mdhp_surrogate* s, const uint16_t* x, int32_t B,
+                                    const float* target, double* loss, void* stream);
+mdhp_status mdhp_surrogate_get_gradients(mdhp_surrogate* s, float* dst, void* stream);
+
+/* One Adam step (bias-corrected) on the master weights with the last
+ * backward pass's gradients; refreshes the BF16 copies. */
+mdhp_status mdhp_surrogate_adam(mdhp_surrogate* s, float lr, float b1, float b2, float eps,
+                                void* stream);
+
+/* backward followed by adam(lr, 0.9, 0.999, 1e-8). */
+mdhp_status mdhp_surrogate_train_step(mdhp_surrogate* s, const uint16_t* x, int32_t B,
+                                      const float* target, float lr, double* loss,
+                                      void* stream);
+
+/* Warm start for a plan with one decay per window.  pred[W][M + M*M + 1]
+ * (device f32) is the network output for the plan's windows, in z-scored
+ * log-parameters: y = pred * stdv + mean gives (log mu, log alpha, log beta)
+ * in the parameter layout order.  Writes mu/alpha/beta = exp(y) (mu and
+ * beta clamped to opts' floors), evaluates ll at them and at the cold start
+ * (mu_cold, alpha_cold, beta_cold), keeps the cold start for windows where
+ * it is at least as likely or the warm one is not finite, and records the
+ * choice in used_warm[W] (1 = warm).  Enqueued on stream. */
+mdhp_status mdhp_warm_start(mdhp_plan* plan, const float* pred, const float* mean,
+                            const float* stdv, const mdhp_fit_opts* opts, const float* mu_cold,
+                            const float* alpha_cold, const float* beta_cold, float* mu,
+                            float* alpha, float* beta, int32_t* used_warm, void* stream);
 
 /* Static description of a status code. */
 const char* mdhp_status_string(mdhp_status status);

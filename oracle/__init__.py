@@ -54,7 +54,7 @@ def _load():
         lib.mdhp_oracle_loglik_brute.argtypes = eval_args + [I32]
         lib.mdhp_oracle_grad.argtypes = eval_args + [P, P, P, I32]
         lib.mdhp_oracle_grad_brute.argtypes = eval_args + [P, P, P, I32]
-        lib.mdhp_oracle_fit.argtypes = [P, P, P, P, I64, I32, I32, P, P, P, P, P, P, P, I32]
+        lib.mdhp_oracle_fit.argtypes = [P, P, P, P, I64, I32, I32, P, P, P, P, P, P, P, P, I32]
         lib.mdhp_oracle_scales.argtypes = eval_args + [P, P, P, I32]
         for f in (lib.mdhp_oracle_loglik, lib.mdhp_oracle_loglik_brute,
                   lib.mdhp_oracle_grad, lib.mdhp_oracle_grad_brute, lib.mdhp_oracle_fit,
@@ -151,8 +151,9 @@ def scales(offsets, t, dim, T, M, mu, alpha, beta, beta_mode=0, nthreads=0):
 class FitOpts:
     """Projected gradient fit options (field order matches the C struct)."""
     max_steps: int = 500
-    optimizer: int = 1  # 0 projected gradient step, 1 projected Adam step
+    optimizer: int = 1  # 0 projected gradient step, 1 projected Adam step, 2 projected L-BFGS
     fix_beta: int = 0
+    history: int = 8
     lr: float = 1e-2
     ll_tol: float = 1e-5
     mu_floor_rel: float = 1e-6
@@ -164,13 +165,13 @@ class FitOpts:
     def pack(self) -> bytes:
         import struct
         return struct.pack("<iiiiddddddd",
-                           self.max_steps, self.optimizer, self.fix_beta, 0,
+                           self.max_steps, self.optimizer, self.fix_beta, self.history,
                            self.lr, self.ll_tol, self.mu_floor_rel, self.beta_floor_rel,
                            self.adam_b1, self.adam_b2, self.adam_eps)
 
 
 def fit(offsets, t, dim, T, M, mu0, alpha0, beta0, opts: FitOpts, beta_mode=0, nthreads=0):
-    """Projected gradient fit; returns (mu, alpha, beta, ll, steps, status)."""
+    """Projected gradient fit; returns (mu, alpha, beta, ll, steps, status, evals)."""
     lib = _load()
     offsets, t, dim, T = _batch(offsets, t, dim, T)
     W = len(T)
@@ -179,10 +180,11 @@ def fit(offsets, t, dim, T, M, mu0, alpha0, beta0, opts: FitOpts, beta_mode=0, n
     ll = np.zeros(W, np.float64)
     steps = np.zeros(W, np.int32)
     status = np.zeros(W, np.int32)
+    evals = np.zeros(W, np.int32)
     buf = ctypes.create_string_buffer(opts.pack())
     rc = lib.mdhp_oracle_fit(_p(offsets), _p(t), _p(dim), _p(T), W, M, beta_mode,
                              ctypes.cast(buf, ctypes.c_void_p), _p(mu), _p(alpha), _p(beta),
-                             _p(ll), _p(steps), _p(status), nthreads)
+                             _p(ll), _p(steps), _p(status), _p(evals), nthreads)
     if rc:
         raise OracleError(f"oracle fit failed: {rc}")
-    return mu, alpha, beta, ll, steps, status
+    return mu, alpha, beta, ll, steps, status, evals

@@ -335,15 +335,146 @@ int eval_batch(const int64_t* offsets, const double* t, const int32_t* dim,
 // the two share no source).
 struct FitOpts {
   int32_t max_steps;
-  int32_t optimizer;  // 0 = projected gradient step, 1 = projected Adam step
+  int32_t optimizer;  // 0 projected gradient step, 1 projected Adam step, 2 projected L-BFGS
   int32_t fix_beta;
-  int32_t reserved;
+  int32_t history;    // L-BFGS memory (0: 8)
   double lr;
   double ll_tol;
   double mu_floor_rel;
   double beta_floor_rel;
   double adam_b1, adam_b2, adam_eps;
 };
+
+// Projected L-BFGS on f = -ll / max(N, 1) with bounds x >= lb (a
+// quasi-Newton variant of the projected update; the paper leaves the
+// optimizer open).  One iteration: variables at their bound whose gradient
+// pushes outward are held fixed; the direction is the two-loop recursion
+// over the last `history` (s, y) pairs applied to the free gradient (scale
+// gamma = s.y / y.y of the newest pair, or 0.01 / max|g| without history),
+// restarted as scaled steepest descent if it is not a descent direction;
+// the step t = 1, 1/2, 1/4, ... (at most 20 trials, each a full likelihood
+// + gradient evaluation) is the first whose projected point satisfies
+// f(x') <= f(x) + 1e-4 g.(x' - x); the pair (x' - x, g' - g) enters the
+// history if its curvature s.y exceeds 1e-10 |s| |y|.  Stops as converged
+// when |ll' - ll| <= ll_tol max(|ll'|, 1) after an accepted step (or when
+// the free gradient vanishes), as MAX_STEPS after max_steps accepted steps,
+// and as STALLED (3) when no trial step is accepted.
+struct LbfgsResult {
+  int steps, status, evals;
+  double ll;
+};
+
+template <class Eval>
+LbfgsResult lbfgs_fit(std::vector<double>& x, const std::vector<double>& lb,
+                      const std::vector<char>& frozen, double inv_n, const FitOpts& o,
+                      Eval eval) {
+  const int P = (int)x.size();
+  const int m = o.history > 0 ? o.history : 8;
+  std::vector<std::vector<double>> S, Y;
+  std::vector<double> rho;
+  std::vector<double> gl(P), g(P), q(P), d(P), xn(P), gn(P);
+  double l = eval(x, gl);
+  int evals = 1;
+  auto finite_all = [&](double v, const std::vector<double>& gv) {
+    if (!std::isfinite(v)) return false;
+    for (double e : gv)
+      if (!std::isfinite(e)) return false;
+    return true;
+  };
+  if (!finite_all(l, gl)) return {0, 2, evals, l};
+  for (int i = 0; i < P; ++i) g[i] = frozen[i] ? 0.0 : -gl[i] * inv_n;
+  double f = -l * inv_n;
+  for (int s = 0;; ++s) {
+    if (s == o.max_steps) return {s, 1, evals, l};
+    double gmax = 0.0;
+    for (int i = 0; i < P; ++i) {
+      const bool active = frozen[i] || (x[i] <= lb[i] && g[i] > 0.0);
+      q[i] = active ? 0.0 : g[i];
+      gmax = std::max(gmax, std::fabs(q[i]));
+    }
+    if (gmax == 0.0) return {s, 0, evals, l};
+    const double gamma0 = 0.01 / gmax;
+    const int h = (int)S.size();
+    std::vector<double> a(h);
+    for (int k = h - 1; k >= 0; --k) {
+      double sq = 0.0;
+      for (int i = 0; i < P; ++i) sq += S[k][i] * q[i];
+      a[k] = rho[k] * sq;
+      for (int i = 0; i < P; ++i) q[i] -= a[k] * Y[k][i];
+    }
+    double gamma = gamma0;
+    if (h > 0) {
+      double sy = 0.0, yy = 0.0;
+      for (int i = 0; i < P; ++i) {
+        sy += S[h - 1][i] * Y[h - 1][i];
+        yy += Y[h - 1][i] * Y[h - 1][i];
+      }
+      gamma = sy / yy;
+    }
+    for (int i = 0; i < P; ++i) q[i] *= gamma;
+    for (int k = 0; k < h; ++k) {
+      double yr = 0.0;
+      for (int i = 0; i < P; ++i) yr += Y[k][i] * q[i];
+      const double b = rho[k] * yr;
+      for (int i = 0; i < P; ++i) q[i] += S[k][i] * (a[k] - b);
+    }
+    double dg = 0.0;
+    for (int i = 0; i < P; ++i) {
+      const bool active = frozen[i] || (x[i] <= lb[i] && g[i] > 0.0);
+      d[i] = active ? 0.0 : -q[i];
+      dg += d[i] * g[i];
+    }
+    if (!(dg < 0.0)) {  // not a descent direction: restart from steepest descent
+      S.clear();
+      Y.clear();
+      rho.clear();
+      for (int i = 0; i < P; ++i) {
+        const bool active = frozen[i] || (x[i] <= lb[i] && g[i] > 0.0);
+        d[i] = active ? 0.0 : -gamma0 * g[i];
+      }
+    }
+    double t = 1.0, ln = 0.0, fn = 0.0;
+    bool ok = false;
+    for (int ls = 0; ls < 20 && !ok; ++ls, t *= 0.5) {
+      double decrease = 0.0;
+      for (int i = 0; i < P; ++i) {
+        xn[i] = std::max(x[i] + t * d[i], lb[i]);
+        decrease += g[i] * (xn[i] - x[i]);
+      }
+      ln = eval(xn, gn);
+      ++evals;
+      fn = -ln * inv_n;
+      ok = finite_all(ln, gn) && fn <= f + 1e-4 * decrease;
+    }
+    if (!ok) return {s, 3, evals, l};
+    std::vector<double> sv(P), yv(P);
+    double sy = 0.0, ss = 0.0, yy = 0.0;
+    for (int i = 0; i < P; ++i) {
+      const double gi = frozen[i] ? 0.0 : -gn[i] * inv_n;
+      sv[i] = xn[i] - x[i];
+      yv[i] = gi - g[i];
+      sy += sv[i] * yv[i];
+      ss += sv[i] * sv[i];
+      yy += yv[i] * yv[i];
+      g[i] = gi;
+      x[i] = xn[i];
+    }
+    if (sy > 1e-10 * std::sqrt(ss * yy)) {
+      if ((int)S.size() == m) {
+        S.erase(S.begin());
+        Y.erase(Y.begin());
+        rho.erase(rho.begin());
+      }
+      S.push_back(sv);
+      Y.push_back(yv);
+      rho.push_back(1.0 / sy);
+    }
+    const double l_prev = l;
+    l = ln;
+    f = fn;
+    if (std::fabs(l - l_prev) <= o.ll_tol * std::max(std::fabs(l), 1.0)) return {s + 1, 0, evals, l};
+  }
+}
 
 }  // namespace
 
@@ -390,18 +521,22 @@ int mdhp_oracle_grad_brute(const int64_t* offsets, const double* t, const int32_
 // s >= 1 and |ll_s - ll_{s-1}| <= ll_tol * max(|ll_s|, 1); stop as not
 // converged when s == max_steps; otherwise theta_{s+1} = Proj(theta_s +
 // step(g_s / max(N, 1))).  The returned theta is theta_s with ll_s, and
-// steps[w] = s (the number of updates applied).  status: 0 converged,
+// steps[w] = s (the number of updates applied), evals[w] (optional) the
+// number of likelihood evaluations.  Optimizer 2 is the projected L-BFGS
+// described at lbfgs_fit.  status: 0 converged,
 // 1 step budget exhausted, 2 non-finite likelihood or gradient (theta_s,
-// the parameters of that evaluation, is returned with its ll).
+// the parameters of that evaluation, is returned with its ll), 3 (L-BFGS)
+// no step of the line search was accepted.
 int mdhp_oracle_fit(const int64_t* offsets, const double* t, const int32_t* dim,
                     const double* T, int64_t W, int32_t M, int32_t beta_mode,
                     const void* opts_ptr, double* mu, double* alpha, double* beta,
-                    double* ll, int32_t* steps, int32_t* status, int32_t nthreads) {
+                    double* ll, int32_t* steps, int32_t* status, int32_t* evals_out,
+                    int32_t nthreads) {
   if (beta_mode != 0 && beta_mode != 1) return -1;
   if (!opts_ptr || !mu || !alpha || !beta || !ll || !steps || !status) return -1;
   FitOpts o;
   std::memcpy(&o, opts_ptr, sizeof(o));
-  if (o.max_steps < 0 || !(o.lr > 0.0) || (o.optimizer != 0 && o.optimizer != 1)) return -1;
+  if (o.max_steps < 0 || !(o.lr > 0.0) || o.optimizer < 0 || o.optimizer > 2) return -1;
   int rc = check_batch(offsets, t, dim, T, W, M);
   if (rc) return rc;
   for (int64_t w = 0; w < W; ++w) {
@@ -423,6 +558,45 @@ int mdhp_oracle_fit(const int64_t* offsets, const double* t, const int32_t* dim,
     std::copy(alpha + w * MM, alpha + (w + 1) * MM, th.begin() + M);
     if (beta_mode == 0) th[M + MM] = beta[w];
     else std::copy(beta + w * MM, beta + (w + 1) * MM, th.begin() + M + MM);
+    if (o.optimizer == 2) {
+      std::vector<double> lb(P, 0.0);
+      std::vector<char> frozen(P, 0);
+      for (int i = 0; i < M; ++i) lb[i] = mu_min;
+      for (int i = M + MM; i < P; ++i) {
+        lb[i] = beta_min;
+        frozen[i] = o.fix_beta ? 1 : 0;
+      }
+      auto eval = [&](const std::vector<double>& x, std::vector<double>& gout) {
+        Params p;
+        p.M = M;
+        p.mu.assign(x.begin(), x.begin() + M);
+        p.alpha.assign(x.begin() + M, x.begin() + M + MM);
+        p.beta.resize(MM);
+        for (int i = 0; i < MM; ++i) p.beta[i] = beta_mode == 0 ? x[M + MM] : x[M + MM + i];
+        Grad g;
+        const double l = recursion_window(win, p, &g);
+        std::copy(g.mu.begin(), g.mu.end(), gout.begin());
+        std::copy(g.alpha.begin(), g.alpha.end(), gout.begin() + M);
+        if (beta_mode == 0) {
+          double sb = 0.0;
+          for (int i = 0; i < MM; ++i) sb += g.beta[i];
+          gout[M + MM] = sb;
+        } else {
+          std::copy(g.beta.begin(), g.beta.end(), gout.begin() + M + MM);
+        }
+        return l;
+      };
+      const LbfgsResult r = lbfgs_fit(th, lb, frozen, inv_n, o, eval);
+      std::copy(th.begin(), th.begin() + M, mu + w * M);
+      std::copy(th.begin() + M, th.begin() + M + MM, alpha + w * MM);
+      if (beta_mode == 0) beta[w] = th[M + MM];
+      else std::copy(th.begin() + M + MM, th.end(), beta + w * MM);
+      ll[w] = r.ll;
+      steps[w] = r.steps;
+      status[w] = r.status;
+      if (evals_out) evals_out[w] = r.evals;
+      return;
+    }
     double ll_prev = 0.0;
     int st = 1, s = 0;
     std::vector<double> th_eval = th;
@@ -492,6 +666,7 @@ int mdhp_oracle_fit(const int64_t* offsets, const double* t, const int32_t* dim,
     ll[w] = ll_eval;
     steps[w] = s;
     status[w] = st;
+    if (evals_out) evals_out[w] = s + 1;
   });
   return 0;
 }

@@ -18,15 +18,19 @@ LIB_PATH = os.path.join(HERE, "libmdhp.so")
 EXPORTS = (
     "mdhp_plan_create", "mdhp_plan_destroy", "mdhp_plan_windows", "mdhp_plan_events",
     "mdhp_plan_dims", "mdhp_loglik", "mdhp_grad", "mdhp_fit_batch", "mdhp_check_params",
-    "mdhp_status_string", "mdhp_last_error",
+    "mdhp_status_string", "mdhp_last_error", "mdhp_features", "mdhp_surrogate_create",
+    "mdhp_surrogate_destroy", "mdhp_surrogate_num_params", "mdhp_surrogate_get_weights",
+    "mdhp_surrogate_set_weights", "mdhp_surrogate_forward", "mdhp_surrogate_get_hidden",
+    "mdhp_surrogate_backward", "mdhp_surrogate_get_gradients", "mdhp_surrogate_adam",
+    "mdhp_surrogate_train_step", "mdhp_warm_start",
 )
 
 MDHP_OK = 0
 STATUS_NAMES = {0: "MDHP_OK", -1: "MDHP_E_INVAL", -2: "MDHP_E_UNSORTED", -3: "MDHP_E_DOMAIN",
                 -4: "MDHP_E_PARAM", -5: "MDHP_E_NOMEM", -6: "MDHP_E_HIP"}
 BETA_SHARED, BETA_PAIR = 0, 1
-OPT_PGD, OPT_PADAM = 0, 1
-FIT_CONVERGED, FIT_MAX_STEPS, FIT_NONFINITE = 0, 1, 2
+OPT_PGD, OPT_PADAM, OPT_LBFGS = 0, 1, 2
+FIT_CONVERGED, FIT_MAX_STEPS, FIT_NONFINITE, FIT_STALLED = 0, 1, 2, 3
 MAX_M = 64
 
 
@@ -38,7 +42,7 @@ class MdhpBatch(ctypes.Structure):
 
 class MdhpFitOpts(ctypes.Structure):
     _fields_ = [("max_steps", ctypes.c_int32), ("optimizer", ctypes.c_int32),
-                ("fix_beta", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("fix_beta", ctypes.c_int32), ("history", ctypes.c_int32),
                 ("lr", ctypes.c_double), ("ll_tol", ctypes.c_double),
                 ("mu_floor_rel", ctypes.c_double), ("beta_floor_rel", ctypes.c_double),
                 ("adam_b1", ctypes.c_double), ("adam_b2", ctypes.c_double),
@@ -74,13 +78,34 @@ def load() -> ctypes.CDLL:
     lib.mdhp_plan_dims.restype = I32
     lib.mdhp_loglik.argtypes = [P, P, P, P, P, P]
     lib.mdhp_grad.argtypes = [P, P, P, P, P, P, P, P, P]
-    lib.mdhp_fit_batch.argtypes = [P, ctypes.POINTER(MdhpFitOpts), P, P, P, P, P, P, P]
+    lib.mdhp_fit_batch.argtypes = [P, ctypes.POINTER(MdhpFitOpts), P, P, P, P, P, P, P, P]
     lib.mdhp_check_params.argtypes = [P, P, P, P, P]
+    lib.mdhp_features.argtypes = [ctypes.POINTER(MdhpBatch), I32, I32, P, P]
+    lib.mdhp_surrogate_create.argtypes = [I32, I32, I32, I32, ctypes.c_uint64, ctypes.POINTER(P)]
+    lib.mdhp_surrogate_destroy.argtypes = [P]
+    lib.mdhp_surrogate_destroy.restype = None
+    lib.mdhp_surrogate_num_params.argtypes = [P]
+    lib.mdhp_surrogate_num_params.restype = I64
+    lib.mdhp_surrogate_get_weights.argtypes = [P, P, P]
+    lib.mdhp_surrogate_set_weights.argtypes = [P, P, P]
+    lib.mdhp_surrogate_get_gradients.argtypes = [P, P, P]
+    lib.mdhp_surrogate_forward.argtypes = [P, P, I32, P, P]
+    lib.mdhp_surrogate_get_hidden.argtypes = [P, I32, P, P, P]
+    lib.mdhp_surrogate_backward.argtypes = [P, P, I32, P, P, P]
+    lib.mdhp_surrogate_adam.argtypes = [P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_float, P]
+    lib.mdhp_surrogate_train_step.argtypes = [P, P, I32, P, ctypes.c_float, P, P]
+    lib.mdhp_warm_start.argtypes = [P, P, P, P, ctypes.POINTER(MdhpFitOpts), P, P, P, P, P, P,
+                                    P, P]
     lib.mdhp_status_string.argtypes = [I32]
     lib.mdhp_status_string.restype = ctypes.c_char_p
     lib.mdhp_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     for name in ("mdhp_plan_create", "mdhp_loglik", "mdhp_grad", "mdhp_fit_batch",
-                 "mdhp_check_params", "mdhp_last_error"):
+                 "mdhp_check_params", "mdhp_last_error", "mdhp_features", "mdhp_surrogate_create",
+                 "mdhp_surrogate_get_weights", "mdhp_surrogate_set_weights",
+                 "mdhp_surrogate_get_gradients", "mdhp_surrogate_forward",
+                 "mdhp_surrogate_get_hidden", "mdhp_surrogate_backward", "mdhp_surrogate_adam",
+                 "mdhp_surrogate_train_step", "mdhp_warm_start"):
         getattr(lib, name).restype = I32
     _lib = lib
     return lib

@@ -14,12 +14,12 @@ import torch
 
 from . import _lib
 from ._lib import (BETA_PAIR, BETA_SHARED, FIT_CONVERGED, FIT_MAX_STEPS, FIT_NONFINITE,
-                   OPT_PADAM, OPT_PGD, MdhpError)
+                   FIT_STALLED, OPT_LBFGS, OPT_PADAM, OPT_PGD, MdhpError)
 
 __all__ = ["Plan", "FitOptions", "mdhp_plan_create", "mdhp_plan_destroy", "mdhp_loglik",
            "mdhp_grad", "mdhp_fit_batch", "mdhp_check_params", "mdhp_status_string",
-           "BETA_SHARED", "BETA_PAIR", "OPT_PGD", "OPT_PADAM", "FIT_CONVERGED",
-           "FIT_MAX_STEPS", "FIT_NONFINITE", "MdhpError"]
+           "BETA_SHARED", "BETA_PAIR", "OPT_PGD", "OPT_PADAM", "OPT_LBFGS", "FIT_CONVERGED",
+           "FIT_MAX_STEPS", "FIT_NONFINITE", "FIT_STALLED", "MdhpError"]
 
 
 def _stream(stream=None) -> int:
@@ -45,6 +45,7 @@ class FitOptions:
     max_steps: int = 500
     optimizer: int = OPT_PADAM
     fix_beta: bool = False
+    history: int = 8
     lr: float = 1e-2
     ll_tol: float = 1e-5
     mu_floor_rel: float = 1e-6
@@ -55,7 +56,7 @@ class FitOptions:
 
     def to_c(self) -> _lib.MdhpFitOpts:
         return _lib.MdhpFitOpts(int(self.max_steps), int(self.optimizer), int(bool(self.fix_beta)),
-                                0, float(self.lr), float(self.ll_tol), float(self.mu_floor_rel),
+                                int(self.history), float(self.lr), float(self.ll_tol), float(self.mu_floor_rel),
                                 float(self.beta_floor_rel), float(self.adam_b1),
                                 float(self.adam_b2), float(self.adam_eps))
 
@@ -96,12 +97,14 @@ def mdhp_grad(handle, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, stream=None) -
                                      ctypes.c_void_p(_stream(stream))))
 
 
-def mdhp_fit_batch(handle, opts: FitOptions, mu, alpha, beta, ll, steps, status,
+def mdhp_fit_batch(handle, opts: FitOptions, mu, alpha, beta, ll, steps, status, evals=None,
                    stream=None) -> None:
     c = opts.to_c()
     _lib.check(_lib.load().mdhp_fit_batch(ctypes.c_void_p(handle), ctypes.byref(c), _ptr(mu),
                                           _ptr(alpha), _ptr(beta), _ptr(ll), _ptr(steps),
-                                          _ptr(status), ctypes.c_void_p(_stream(stream))))
+                                          _ptr(status),
+                                          _ptr(evals) if evals is not None else None,
+                                          ctypes.c_void_p(_stream(stream))))
 
 
 def mdhp_check_params(handle, mu, alpha, beta, stream=None) -> None:
@@ -165,14 +168,18 @@ class Plan:
         mdhp_grad(self.handle, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, stream)
         return ll, g_mu, g_alpha, g_beta
 
-    def fit(self, mu, alpha, beta, opts: FitOptions | None = None, stream=None):
-        """Fits every window; returns (mu, alpha, beta, ll, steps, status)."""
+    def fit(self, mu, alpha, beta, opts: FitOptions | None = None, stream=None,
+            return_evals: bool = False):
+        """Fits every window; returns (mu, alpha, beta, ll, steps, status[, evals])."""
         opts = opts or FitOptions()
         mu, alpha, beta = (x.clone() for x in self._params(mu, alpha, beta))
         ll = torch.empty(self.W, dtype=torch.float64, device=self.device)
         steps = torch.empty(self.W, dtype=torch.int32, device=self.device)
         status = torch.empty(self.W, dtype=torch.int32, device=self.device)
-        mdhp_fit_batch(self.handle, opts, mu, alpha, beta, ll, steps, status, stream)
+        evals = torch.empty(self.W, dtype=torch.int32, device=self.device)
+        mdhp_fit_batch(self.handle, opts, mu, alpha, beta, ll, steps, status, evals, stream)
+        if return_evals:
+            return mu, alpha, beta, ll, steps, status, evals
         return mu, alpha, beta, ll, steps, status
 
     def check_params(self, mu, alpha, beta, stream=None) -> None:

@@ -22,6 +22,9 @@ struct mdhp_plan {
   int32_t* order = nullptr;
   int* counter = nullptr;  // window queue head
   int* flags = nullptr;    // [0] error bits of prepare / check_params
+  double* ll_ws = nullptr; // [2 W] likelihoods of the warm and cold starts
+  float* fit_ws = nullptr; // L-BFGS per-workgroup vectors
+  int64_t fit_ws_floats = 0;
   uint32_t magic = 0;
 };
 
@@ -30,23 +33,28 @@ namespace mdhp {
 __global__ void reset_counter_kernel(int* counter) { *counter = 0; }
 
 namespace {
-
-constexpr uint32_t kMagic = 0x4d444850u;  // "MDHP"
-constexpr int kErrUnsorted = 1, kErrDomain = 2, kErrParam = 4;
-
 thread_local std::string g_last_msg;
 thread_local mdhp_status g_last_status = MDHP_OK;
+}  // namespace
 
-mdhp_status fail(mdhp_status s, const std::string& msg) {
+mdhp_status mdhp_fail(mdhp_status s, const std::string& msg) {
   g_last_status = s;
   g_last_msg = msg;
   return s;
 }
 
-mdhp_status hip_fail(hipError_t e, const char* where) {
-  return fail(e == hipErrorOutOfMemory ? MDHP_E_NOMEM : MDHP_E_HIP,
-              std::string(where) + ": " + hipGetErrorString(e));
+mdhp_status mdhp_hip_fail(hipError_t e, const char* where) {
+  return mdhp_fail(e == hipErrorOutOfMemory ? MDHP_E_NOMEM : MDHP_E_HIP,
+                   std::string(where) + ": " + hipGetErrorString(e));
 }
+
+namespace {
+
+constexpr uint32_t kMagic = 0x4d444850u;  // "MDHP"
+constexpr int kErrUnsorted = 1, kErrDomain = 2, kErrParam = 4;
+
+mdhp_status fail(mdhp_status s, const std::string& msg) { return mdhp_fail(s, msg); }
+mdhp_status hip_fail(hipError_t e, const char* where) { return mdhp_hip_fail(e, where); }
 
 // Sec. IV-B "Stage 1" counterpart: per event, the gap to the previous event
 // of the same window in FP64 (stored FP32; a positive gap never rounds to 0),
@@ -122,6 +130,8 @@ void free_plan(mdhp_plan* p) {
   (void)hipFree(p->order);
   (void)hipFree(p->counter);
   (void)hipFree(p->flags);
+  (void)hipFree(p->ll_ws);
+  (void)hipFree(p->fit_ws);
   p->magic = 0;
   delete p;
 }
@@ -161,6 +171,8 @@ mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, 
   if (M < 1 || M > MDHP_MAX_M) return fail(MDHP_E_INVAL, "plan_create: M must be in [1, 64]");
   if (beta_mode != MDHP_BETA_SHARED && beta_mode != MDHP_BETA_PAIR)
     return fail(MDHP_E_INVAL, "plan_create: unknown beta_mode");
+  if (beta_mode == MDHP_BETA_PAIR && M > MDHP_MAX_M_PAIR)
+    return fail(MDHP_E_INVAL, "plan_create: per-pair decays support M <= 32");
   if (b->W < 0 || b->n_events < 0) return fail(MDHP_E_INVAL, "plan_create: negative sizes");
   if (b->W > INT32_MAX) return fail(MDHP_E_INVAL, "plan_create: too many windows");
   if (!b->offsets || (b->W > 0 && !b->T) || (b->n_events > 0 && (!b->t || !b->dim)))
@@ -192,7 +204,11 @@ mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, 
       (e = dev_alloc(&p->T, W)) != hipSuccess || (e = dev_alloc(&p->end_gap, W)) != hipSuccess ||
       (e = dev_alloc(&p->order, W)) != hipSuccess ||
       (e = dev_alloc(&p->counter, 1)) != hipSuccess ||
-      (e = dev_alloc(&p->flags, 1)) != hipSuccess) {
+      (e = dev_alloc(&p->flags, 1)) != hipSuccess ||
+      (e = dev_alloc(&p->ll_ws, 2 * W)) != hipSuccess ||
+      (beta_mode == MDHP_BETA_SHARED &&
+       (e = dev_alloc(&p->fit_ws, (size_t)(p->fit_ws_floats = shared_lbfgs_workspace(M, W)))) !=
+           hipSuccess)) {
     free_plan(p);
     return hip_fail(e, "plan_create: allocation");
   }
@@ -280,26 +296,65 @@ mdhp_status mdhp_grad(mdhp_plan* p, const float* mu, const float* alpha, const f
 
 mdhp_status mdhp_fit_batch(mdhp_plan* p, const mdhp_fit_opts* o, float* mu, float* alpha,
                            float* beta, double* ll, int32_t* steps, int32_t* status,
-                           void* stream) {
+                           int32_t* evals, void* stream) {
   if (!plan_ok(p)) return fail(MDHP_E_INVAL, "fit_batch: invalid plan");
   if (!o) return fail(MDHP_E_INVAL, "fit_batch: opts is NULL");
   if (p->W > 0 && (!mu || !alpha || !beta || !ll || !steps || !status))
     return fail(MDHP_E_INVAL, "fit_batch: null pointer");
-  if (o->max_steps < 0 || !(o->lr > 0.0) || !std::isfinite(o->lr) || !(o->ll_tol >= 0.0) ||
-      (o->optimizer != MDHP_OPT_PGD && o->optimizer != MDHP_OPT_PADAM) || o->reserved != 0 ||
+  if (o->max_steps < 0 || !(o->ll_tol >= 0.0) ||
+      (o->optimizer != MDHP_OPT_LBFGS && (!(o->lr > 0.0) || !std::isfinite(o->lr))) ||
+      (o->optimizer != MDHP_OPT_PGD && o->optimizer != MDHP_OPT_PADAM &&
+       o->optimizer != MDHP_OPT_LBFGS) ||
+      o->history < 0 || o->history > MDHP_MAX_HISTORY ||
       !(o->mu_floor_rel >= 0.0) || !(o->beta_floor_rel >= 0.0) ||
       (o->optimizer == MDHP_OPT_PADAM &&
        !(o->adam_b1 >= 0.0 && o->adam_b1 < 1.0 && o->adam_b2 >= 0.0 && o->adam_b2 < 1.0 &&
          o->adam_eps >= 0.0)))
     return fail(MDHP_E_INVAL, "fit_batch: invalid options");
-  FitParams fp{o->max_steps, o->optimizer, o->fix_beta,  o->lr,      o->ll_tol,
-               o->mu_floor_rel, o->beta_floor_rel, o->adam_b1, o->adam_b2, o->adam_eps};
+  if (o->optimizer == MDHP_OPT_LBFGS && p->beta_mode != MDHP_BETA_SHARED)
+    return fail(MDHP_E_INVAL, "fit_batch: L-BFGS needs one decay per window");
+  FitParams fp{o->max_steps,  o->optimizer,      o->fix_beta, o->history > 0 ? o->history : 8,
+               o->lr,         o->ll_tol,         o->mu_floor_rel, o->beta_floor_rel,
+               o->adam_b1,    o->adam_b2,        o->adam_eps};
   hipStream_t s = (hipStream_t)stream;
   const Events ev = events_of(p);
   hipError_t e = p->beta_mode == MDHP_BETA_SHARED
-                     ? shared_fit(ev, p->M, fp, mu, alpha, beta, ll, steps, status, p->counter, s)
-                     : pair_fit(ev, p->M, fp, mu, alpha, beta, ll, steps, status, p->counter, s);
+                     ? shared_fit(ev, p->M, fp, mu, alpha, beta, ll, steps, status, evals,
+                                  p->fit_ws, p->fit_ws_floats, p->counter, s)
+                     : pair_fit(ev, p->M, fp, mu, alpha, beta, ll, steps, status, evals,
+                                p->counter, s);
   if (e != hipSuccess) return hip_fail(e, "fit_batch: launch");
+  return MDHP_OK;
+}
+
+mdhp_status mdhp_warm_start(mdhp_plan* p, const float* pred, const float* mean,
+                            const float* stdv, const mdhp_fit_opts* o, const float* mu_cold,
+                            const float* alpha_cold, const float* beta_cold, float* mu,
+                            float* alpha, float* beta, int32_t* used_warm, void* stream) {
+  if (!plan_ok(p)) return fail(MDHP_E_INVAL, "warm_start: invalid plan");
+  if (p->beta_mode != MDHP_BETA_SHARED)
+    return fail(MDHP_E_INVAL, "warm_start: needs one decay per window");
+  if (!o) return fail(MDHP_E_INVAL, "warm_start: opts is NULL");
+  if (p->W == 0) return MDHP_OK;
+  if (!pred || !mean || !stdv || !mu_cold || !alpha_cold || !beta_cold || !mu || !alpha ||
+      !beta || !used_warm)
+    return fail(MDHP_E_INVAL, "warm_start: null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  const Events ev = events_of(p);
+  double* ll_w = p->ll_ws;
+  double* ll_c = p->ll_ws + p->W;
+  hipError_t e = warm_params(pred, mean, stdv, p->n, p->T, p->W, p->M, (float)o->mu_floor_rel,
+                             (float)o->beta_floor_rel, mu, alpha, beta, s);
+  if (e == hipSuccess)
+    e = shared_eval(ev, p->M, mu, alpha, beta, ll_w, nullptr, nullptr, nullptr, p->counter, s,
+                    false);
+  if (e == hipSuccess)
+    e = shared_eval(ev, p->M, mu_cold, alpha_cold, beta_cold, ll_c, nullptr, nullptr, nullptr,
+                    p->counter, s, false);
+  if (e == hipSuccess)
+    e = choose_init(ll_w, ll_c, p->W, p->M, mu_cold, alpha_cold, beta_cold, mu, alpha, beta,
+                    used_warm, s);
+  if (e != hipSuccess) return hip_fail(e, "warm_start");
   return MDHP_OK;
 }
 

@@ -1,0 +1,75 @@
+// Device helpers shared by the library's kernels: cross-lane operations
+// within groups of P consecutive lanes of a 64-wide wavefront.
+#pragma once
+
+#include <utility>
+
+#include "mdhp_internal.h"
+
+namespace mdhp {
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the P consecutive lanes of a group; every lane gets the sum.
+template <int P>
+__device__ __forceinline__ float group_sum(float v) {
+  if constexpr (P >= 2) v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+  if constexpr (P >= 4) v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+  if constexpr (P >= 8) v += dpp<0x141>(v);  // row_half_mirror: the other quad of the 8
+  if constexpr (P >= 16) v += dpp<0x140>(v); // row_mirror: the other 8 of the 16-lane row
+  if constexpr (P >= 32) v += __shfl_xor(v, 16);
+  if constexpr (P >= 64) v += __shfl_xor(v, 32);
+  return v;
+}
+
+// Lane J of the caller's group, broadcast to the whole group (J < P).
+template <int P, int J>
+__device__ __forceinline__ float group_bcast(float x) {
+  const int v = __builtin_bit_cast(int, x);
+  int r;
+  if constexpr (P == 4) r = __builtin_amdgcn_mov_dpp(v, J * 0x55, 0xF, 0xF, false);  // quad_perm [J,J,J,J]
+  else if constexpr (P == 8) r = __builtin_amdgcn_ds_swizzle(v, 0x18 | (J << 5));      // (lane & 24) | J
+  else if constexpr (P == 16) r = __builtin_amdgcn_mov_dpp(v, 0x150 + J, 0xF, 0xF, false);  // row_newbcast
+  else if constexpr (P == 32) r = __builtin_amdgcn_ds_swizzle(v, J << 5);              // lane J of the 32
+  else r = __builtin_amdgcn_readlane(v, J);
+  return __builtin_bit_cast(float, r);
+}
+
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+
+// f(std::integral_constant<int, j>) for j = 0 .. N-1, fully unrolled.
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Inclusive prefix sum over the P lanes of a group (lane order).
+template <int P>
+__device__ __forceinline__ float group_scan(float v, int lane) {
+#pragma unroll
+  for (int k = 1; k < P; k <<= 1) {
+    const float y = __shfl_up(v, k, P);
+    if (lane >= k) v += y;
+  }
+  return v;
+}
+
+
+template <class K>
+int occupancy_grid(K kernel, int threads, int64_t W) {
+  int dev = 0, cus = 0, per_cu = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0);
+  int64_t g = (int64_t)std::max(cus, 1) * std::max(per_cu, 1);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, W));
+}
+
+}  // namespace mdhp

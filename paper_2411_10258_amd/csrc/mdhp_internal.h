@@ -5,12 +5,14 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <string>
 
 #include "mdhp.h"
 
 namespace mdhp {
 
 constexpr int kBlock = 256;  // threads per workgroup (4 waves of 64)
+constexpr int kMaxHistory = 16;  // largest L-BFGS memory
 
 // FP64 G_R accumulators each thread owns for a P x P matrix.
 constexpr int own_count(int P) { return P * P >= kBlock ? P * P / kBlock : 1; }
@@ -39,10 +41,22 @@ struct FitParams {
   int max_steps;
   int optimizer;
   int fix_beta;
+  int history;
   double lr, ll_tol, mu_floor_rel, beta_floor_rel, b1, b2, eps;
 };
 
 __global__ void reset_counter_kernel(int* counter);
+
+// Records the calling thread's last error and returns its status.
+mdhp_status mdhp_fail(mdhp_status s, const std::string& msg);
+mdhp_status mdhp_hip_fail(hipError_t e, const char* where);
+
+hipError_t warm_params(const float* pred, const float* mean, const float* stdv,
+                       const int32_t* n, const double* T, int64_t W, int M, float mu_floor_rel,
+                       float beta_floor_rel, float* mu, float* alpha, float* beta, hipStream_t s);
+hipError_t choose_init(const double* ll_warm, const double* ll_cold, int64_t W, int M,
+                       const float* mu_c, const float* al_c, const float* be_c, float* mu,
+                       float* alpha, float* beta, int32_t* used_warm, hipStream_t s);
 
 inline void reset_counter(int* counter, hipStream_t s) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
@@ -52,13 +66,15 @@ hipError_t shared_eval(const Events& ev, int M, const float* mu, const float* al
                        const float* beta, double* ll, float* g_mu, float* g_alpha, float* g_beta,
                        int* counter, hipStream_t s, bool grad);
 hipError_t shared_fit(const Events& ev, int M, const FitParams& o, float* mu, float* alpha,
-                      float* beta, double* ll, int* steps, int* status, int* counter,
-                      hipStream_t s);
+                      float* beta, double* ll, int* steps, int* status, int* evals, float* ws,
+                      int64_t ws_floats, int* counter, hipStream_t s);
+// Floats of workspace the L-BFGS fit needs for a plan of W windows.
+int64_t shared_lbfgs_workspace(int M, int64_t W);
 hipError_t pair_eval(const Events& ev, int M, const float* mu, const float* alpha,
                      const float* beta, double* ll, float* g_mu, float* g_alpha, float* g_beta,
                      int* counter, hipStream_t s, bool grad);
 hipError_t pair_fit(const Events& ev, int M, const FitParams& o, float* mu, float* alpha,
-                    float* beta, double* ll, int* steps, int* status, int* counter,
+                    float* beta, double* ll, int* steps, int* status, int* evals, int* counter,
                     hipStream_t s);
 
 }  // namespace mdhp

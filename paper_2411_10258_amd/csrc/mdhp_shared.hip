@@ -28,66 +28,11 @@
 // which are the scan state advanced from the last event to T.
 // Per-lane FP32 partial sums are reduced in FP64 at the end of the window.
 
-#include <utility>
-
-#include "mdhp_internal.h"
+#include "mdhp_device.h"
 
 namespace mdhp {
 
 namespace {
-
-template <int CTRL>
-__device__ __forceinline__ float dpp(float v) {
-  return __builtin_bit_cast(
-      float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
-}
-
-// Sum over the P consecutive lanes of a group; every lane gets the sum.
-template <int P>
-__device__ __forceinline__ float group_sum(float v) {
-  if constexpr (P >= 2) v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
-  if constexpr (P >= 4) v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
-  if constexpr (P >= 8) v += dpp<0x141>(v);  // row_half_mirror: the other quad of the 8
-  if constexpr (P >= 16) v += dpp<0x140>(v); // row_mirror: the other 8 of the 16-lane row
-  if constexpr (P >= 32) v += __shfl_xor(v, 16);
-  if constexpr (P >= 64) v += __shfl_xor(v, 32);
-  return v;
-}
-
-// Lane J of the caller's group, broadcast to the whole group (J < P).
-template <int P, int J>
-__device__ __forceinline__ float group_bcast(float x) {
-  const int v = __builtin_bit_cast(int, x);
-  int r;
-  if constexpr (P == 4) r = __builtin_amdgcn_mov_dpp(v, J * 0x55, 0xF, 0xF, false);  // quad_perm [J,J,J,J]
-  else if constexpr (P == 8) r = __builtin_amdgcn_ds_swizzle(v, 0x18 | (J << 5));      // (lane & 24) | J
-  else if constexpr (P == 16) r = __builtin_amdgcn_mov_dpp(v, 0x150 + J, 0xF, 0xF, false);  // row_newbcast
-  else if constexpr (P == 32) r = __builtin_amdgcn_ds_swizzle(v, J << 5);              // lane J of the 32
-  else r = __builtin_amdgcn_readlane(v, J);
-  return __builtin_bit_cast(float, r);
-}
-
-template <class F, int... Is>
-__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, Is...>) {
-  (f(std::integral_constant<int, Is>{}), ...);
-}
-
-// f(std::integral_constant<int, j>) for j = 0 .. N-1, fully unrolled.
-template <int N, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  static_for_impl(f, std::make_integer_sequence<int, N>{});
-}
-
-// Inclusive prefix sum over the P lanes of a group (lane order).
-template <int P>
-__device__ __forceinline__ float group_scan(float v, int lane) {
-#pragma unroll
-  for (int k = 1; k < P; k <<= 1) {
-    const float y = __shfl_up(v, k, P);
-    if (lane >= k) v += y;
-  }
-  return v;
-}
 
 #ifndef MDHP_BATCH
 #define MDHP_BATCH 16
@@ -419,7 +364,7 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void shared_fit_kernel(Events ev, int M, FitParams o,
                                                             float* mu, float* alpha, float* beta,
                                                             double* ll, int* steps, int* status,
-                                                            int* counter) {
+                                                            int* evals_out, int* counter) {
   __shared__ SharedLds<P> sh;
   constexpr int OWN = own_count(P);
   double gR64[OWN];
@@ -514,18 +459,296 @@ __global__ __launch_bounds__(kBlock) void shared_fit_kernel(Events ev, int M, Fi
       ll[w] = sh.scal[0];
       steps[w] = s;
       status[w] = st;
+      if (evals_out) evals_out[w] = s + 1;
     }
   }
 }
 
-template <class K>
-int occupancy_grid(K kernel, int64_t W) {
-  int dev = 0, cus = 0, per_cu = 0;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0);
-  int64_t g = (int64_t)std::max(cus, 1) * std::max(per_cu, 1);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(g, W));
+// Block-wide sums of NV doubles (every thread gets the sums).
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&v)[NV], double* scratch) {
+#pragma unroll
+  for (int j = 0; j < NV; ++j)
+#pragma unroll
+    for (int k = 32; k > 0; k >>= 1) v[j] += __shfl_xor(v[j], k, 64);
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) scratch[j * 4 + wave] = v[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NV; ++j)
+    v[j] = scratch[j * 4 + 0] + scratch[j * 4 + 1] + scratch[j * 4 + 2] + scratch[j * 4 + 3];
+}
+
+__device__ __forceinline__ double block_max_abs(double v, double* scratch) {
+  v = fabs(v);
+#pragma unroll
+  for (int k = 32; k > 0; k >>= 1) v = fmax(v, __shfl_xor(v, k, 64));
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[wave] = v;
+  __syncthreads();
+  return fmax(fmax(scratch[0], scratch[1]), fmax(scratch[2], scratch[3]));
+}
+
+// Projected L-BFGS fit (the update rule is described with the options in
+// the public header).  Thread tid owns parameter slots k < OWN: alpha
+// entry e = tid + k * kBlock (row e / P, column e % P), and slot OWN: mu_tid
+// (tid < M) or beta (tid == M).  Its slices of x, g, d and of the history
+// pairs live in a per-workgroup region of the global workspace that only it
+// reads and writes; the scalars of the two-loop recursion come from block
+// reductions.
+template <int P>
+__global__ __launch_bounds__(kBlock) void shared_lbfgs_kernel(Events ev, int M, FitParams o,
+                                                              float* mu, float* alpha,
+                                                              float* beta, double* ll,
+                                                              int* steps, int* status,
+                                                              int* evals_out, float* ws,
+                                                              int* counter) {
+  __shared__ SharedLds<P> sh;
+  __shared__ double scratch[16];
+  __shared__ double a_s[kMaxHistory], rho_s[kMaxHistory];
+  __shared__ int flag;
+  constexpr int OWN = own_count(P);
+  constexpr int K = OWN + 1;
+  double gR64[OWN];
+  const int tid = threadIdx.x;
+  const int m_hist = o.history;
+  // Workspace of this workgroup: X, G, D, XN then S[m], Y[m]; slot (k, tid).
+  float* base = ws + (size_t)blockIdx.x * (size_t)(4 + 2 * kMaxHistory) * K * kBlock;
+  auto X = [&](int k) -> float& { return base[(0 * K + k) * kBlock + tid]; };
+  auto Gv = [&](int k) -> float& { return base[(1 * K + k) * kBlock + tid]; };
+  auto D = [&](int k) -> float& { return base[(2 * K + k) * kBlock + tid]; };
+  auto XN = [&](int k) -> float& { return base[(3 * K + k) * kBlock + tid]; };
+  auto Sv = [&](int j, int k) -> float& { return base[((4 + j) * K + k) * kBlock + tid]; };
+  auto Yv = [&](int j, int k) -> float& {
+    return base[((4 + kMaxHistory + j) * K + k) * kBlock + tid];
+  };
+  zero_accumulators(sh);
+  for (int q = next_window(sh, counter, 1); q < ev.W; q = next_window(sh, counter, 0)) {
+    const int64_t w = ev.order[q];
+    load_params(sh, mu, alpha, beta, w, M);
+    const int n = ev.n[w];
+    const double T = ev.T[w];
+    const double rate = (double)max(n, 1) / T;
+    const float mu_min = (float)(o.mu_floor_rel * rate);
+    const float beta_min = (float)(o.beta_floor_rel * rate);
+    const double inv_n = 1.0 / (double)max(n, 1);
+    // Slot kinds: 0 none, 1 alpha, 2 mu, 3 beta (frozen when fix_beta).
+    auto kind = [&](int k) -> int {
+      if (k < OWN) {
+        const int e = tid + k * kBlock;
+        return (e < P * P && e / P < M && e % P < M) ? 1 : 0;
+      }
+      if (tid < M) return 2;
+      if (tid == M) return o.fix_beta ? 0 : 3;
+      return 0;
+    };
+    auto lower = [&](int k) -> float {
+      const int kd = kind(k);
+      return kd == 2 ? mu_min : (kd == 3 ? beta_min : 0.f);
+    };
+    auto get_param = [&](int k) -> float {
+      const int kd = kind(k);
+      if (kd == 1) return sh.alpha[tid + k * kBlock];
+      if (kd == 2) return sh.mu[tid];
+      if (kd == 3) return sh.beta;
+      return 0.f;
+    };
+    auto set_param = [&](int k, float v) {
+      const int kd = kind(k);
+      if (kd == 1) sh.alpha[tid + k * kBlock] = v;
+      else if (kd == 2) sh.mu[tid] = v;
+      else if (kd == 3) sh.beta = v;
+    };
+    // Gradient of f = -ll / N for slot k after eval_window.
+    auto grad_f = [&](int k) -> double {
+      const int kd = kind(k);
+      if (kd == 1) return -(gR64[k] - sh.Cn[(tid + k * kBlock) % P]) * inv_n;
+      if (kd == 2) return -sh.gmu[tid] * inv_n;
+      if (kd == 3) return -sh.scal[1] * inv_n;
+      return 0.0;
+    };
+    auto refresh_colsum = [&]() {
+      __syncthreads();
+      if (tid < P) {
+        float cs = 0.f;
+        for (int m = 0; m < M; ++m) cs += sh.alpha[m * P + tid];
+        sh.colsum[tid] = cs;
+      }
+      __syncthreads();
+    };
+    // Evaluates at the LDS parameters; true if ll and the gradient are finite.
+    auto evaluate = [&]() -> bool {
+      eval_window<P, true>(sh, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], M, gR64);
+      if (tid == 0) flag = isfinite(sh.scal[0]) && isfinite(sh.scal[1]) ? 0 : 1;
+      __syncthreads();
+      bool bad = false;
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (!isfinite(grad_f(k))) bad = true;
+      if (bad) atomicOr(&flag, 1);
+      __syncthreads();
+      return flag == 0;
+    };
+    int nev = 1, st = MDHP_FIT_MAX_STEPS, s = 0, h = 0, head = 0;
+    double l = 0.0, sy_new = 0.0, yy_new = 0.0;
+    if (!evaluate()) {
+      st = MDHP_FIT_NONFINITE;
+      l = sh.scal[0];
+    } else {
+      l = sh.scal[0];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        X(k) = get_param(k);
+        Gv(k) = (float)grad_f(k);
+      }
+      double f = -l * inv_n;
+      for (s = 0;; ++s) {
+        if (s == o.max_steps) {
+          st = MDHP_FIT_MAX_STEPS;
+          break;
+        }
+        // Free gradient and its largest entry.
+        double qv[K], gmax_local = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float g = Gv(k);
+          const bool active = kind(k) == 0 || (X(k) <= lower(k) && g > 0.f);
+          qv[k] = active ? 0.0 : (double)g;
+          gmax_local = fmax(gmax_local, fabs(qv[k]));
+        }
+        const double gmax = block_max_abs(gmax_local, scratch);
+        if (gmax == 0.0) {
+          st = MDHP_FIT_CONVERGED;
+          break;
+        }
+        const double gamma0 = 0.01 / gmax;
+        for (int i = 0; i < h; ++i) {
+          const int j = (head - 1 - i + kMaxHistory) % kMaxHistory;
+          double v[1] = {0.0};
+#pragma unroll
+          for (int k = 0; k < K; ++k) v[0] += (double)Sv(j, k) * qv[k];
+          block_sums<1>(v, scratch);
+          const double a = rho_s[j] * v[0];
+          if (tid == 0) a_s[j] = a;
+#pragma unroll
+          for (int k = 0; k < K; ++k) qv[k] -= a * (double)Yv(j, k);
+        }
+        const double gamma = h > 0 ? sy_new / yy_new : gamma0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) qv[k] *= gamma;
+        for (int i = h - 1; i >= 0; --i) {
+          const int j = (head - 1 - i + kMaxHistory) % kMaxHistory;
+          double v[1] = {0.0};
+#pragma unroll
+          for (int k = 0; k < K; ++k) v[0] += (double)Yv(j, k) * qv[k];
+          block_sums<1>(v, scratch);
+          const double b = rho_s[j] * v[0];
+          const double a = a_s[j];
+#pragma unroll
+          for (int k = 0; k < K; ++k) qv[k] += (a - b) * (double)Sv(j, k);
+        }
+        double dg[1] = {0.0};
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float g = Gv(k);
+          const bool active = kind(k) == 0 || (X(k) <= lower(k) && g > 0.f);
+          const double dk = active ? 0.0 : -qv[k];
+          D(k) = (float)dk;
+          dg[0] += dk * (double)g;
+        }
+        block_sums<1>(dg, scratch);
+        if (!(dg[0] < 0.0)) {  // restart from scaled steepest descent
+          h = 0;
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const float g = Gv(k);
+            const bool active = kind(k) == 0 || (X(k) <= lower(k) && g > 0.f);
+            D(k) = active ? 0.f : (float)(-gamma0 * (double)g);
+          }
+        }
+        // Backtracking line search on the projected path.
+        double t = 1.0, ln = 0.0, fn = 0.0;
+        bool ok = false;
+        for (int ls = 0; ls < 20 && !ok; ++ls, t *= 0.5) {
+          double dec[1] = {0.0};
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            if (kind(k) == 0) continue;
+            const float x0 = X(k);
+            const float xn = fmaxf((float)((double)x0 + t * (double)D(k)), lower(k));
+            XN(k) = xn;
+            set_param(k, xn);
+            dec[0] += (double)Gv(k) * ((double)xn - (double)x0);
+          }
+          block_sums<1>(dec, scratch);
+          refresh_colsum();
+          const bool fin = evaluate();
+          ++nev;
+          ln = sh.scal[0];
+          fn = -ln * inv_n;
+          ok = fin && fn <= f + 1e-4 * dec[0];
+        }
+        if (!ok) {
+          st = MDHP_FIT_STALLED;
+#pragma unroll
+          for (int k = 0; k < K; ++k) set_param(k, X(k));
+          __syncthreads();
+          break;
+        }
+        double sums[3] = {0.0, 0.0, 0.0};  // s.y, s.s, y.y
+        float sk[K], yk[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float gn = (float)grad_f(k);
+          const float xn = kind(k) == 0 ? X(k) : XN(k);
+          sk[k] = xn - X(k);
+          yk[k] = gn - Gv(k);
+          sums[0] += (double)sk[k] * (double)yk[k];
+          sums[1] += (double)sk[k] * (double)sk[k];
+          sums[2] += (double)yk[k] * (double)yk[k];
+          X(k) = xn;
+          Gv(k) = gn;
+        }
+        block_sums<3>(sums, scratch);
+        if (sums[0] > 1e-10 * sqrt(sums[1] * sums[2])) {
+          if (h == m_hist) h -= 1;  // the oldest pair drops out of the ring
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            Sv(head, k) = sk[k];
+            Yv(head, k) = yk[k];
+          }
+          if (tid == 0) rho_s[head] = 1.0 / sums[0];
+          sy_new = sums[0];
+          yy_new = sums[2];
+          head = (head + 1) % kMaxHistory;
+          h += 1;
+          __syncthreads();
+        }
+        const double l_prev = l;
+        l = ln;
+        f = fn;
+        if (fabs(l - l_prev) <= o.ll_tol * fmax(fabs(l), 1.0)) {
+          st = MDHP_FIT_CONVERGED;
+          s += 1;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < M * M; e += kBlock) alpha[w * M * M + e] = sh.alpha[(e / M) * P + e % M];
+    if (tid < M) mu[w * M + tid] = sh.mu[tid];
+    if (tid == 0) {
+      beta[w] = sh.beta;
+      ll[w] = l;
+      steps[w] = s;
+      status[w] = st;
+      if (evals_out) evals_out[w] = nev;
+    }
+  }
 }
 
 template <int P>
@@ -536,11 +759,11 @@ hipError_t launch_shared_eval(const Events& ev, int M, const float* mu, const fl
   reset_counter(counter, s);
   if (grad) {
     auto k = shared_eval_kernel<P, true>;
-    hipLaunchKernelGGL(k, dim3(occupancy_grid(k, ev.W)), dim3(kBlock), 0, s, ev, M, mu, alpha,
+    hipLaunchKernelGGL(k, dim3(occupancy_grid(k, kBlock, ev.W)), dim3(kBlock), 0, s, ev, M, mu, alpha,
                        beta, ll, g_mu, g_alpha, g_beta, counter);
   } else {
     auto k = shared_eval_kernel<P, false>;
-    hipLaunchKernelGGL(k, dim3(occupancy_grid(k, ev.W)), dim3(kBlock), 0, s, ev, M, mu, alpha,
+    hipLaunchKernelGGL(k, dim3(occupancy_grid(k, kBlock, ev.W)), dim3(kBlock), 0, s, ev, M, mu, alpha,
                        beta, ll, g_mu, g_alpha, g_beta, counter);
   }
   return hipGetLastError();
@@ -549,13 +772,29 @@ hipError_t launch_shared_eval(const Events& ev, int M, const float* mu, const fl
 template <int P>
 hipError_t launch_shared_fit(const Events& ev, int M, const FitParams& o, float* mu,
                              float* alpha, float* beta, double* ll, int* steps, int* status,
-                             int* counter, hipStream_t s) {
+                             int* evals, float* ws, int64_t ws_floats, int* counter,
+                             hipStream_t s) {
   if (ev.W == 0) return hipSuccess;
   reset_counter(counter, s);
+  if (o.optimizer == MDHP_OPT_LBFGS) {
+    auto k = shared_lbfgs_kernel<P>;
+    const int64_t per_block = (int64_t)(4 + 2 * kMaxHistory) * (own_count(P) + 1) * kBlock;
+    const int grid = (int)std::min<int64_t>(occupancy_grid(k, kBlock, ev.W), ws_floats / per_block);
+    if (grid < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), 0, s, ev, M, o, mu, alpha, beta, ll, steps,
+                       status, evals, ws, counter);
+    return hipGetLastError();
+  }
   auto k = shared_fit_kernel<P>;
-  hipLaunchKernelGGL(k, dim3(occupancy_grid(k, ev.W)), dim3(kBlock), 0, s, ev, M, o, mu, alpha,
-                     beta, ll, steps, status, counter);
+  hipLaunchKernelGGL(k, dim3(occupancy_grid(k, kBlock, ev.W)), dim3(kBlock), 0, s, ev, M, o, mu,
+                     alpha, beta, ll, steps, status, evals, counter);
   return hipGetLastError();
+}
+
+template <int P>
+int64_t shared_lbfgs_ws(int64_t W) {
+  const int64_t per_block = (int64_t)(4 + 2 * kMaxHistory) * (own_count(P) + 1) * kBlock;
+  return per_block * occupancy_grid(shared_lbfgs_kernel<P>, kBlock, std::max<int64_t>(W, 1));
 }
 
 }  // namespace
@@ -573,14 +812,24 @@ hipError_t shared_eval(const Events& ev, int M, const float* mu, const float* al
 }
 
 hipError_t shared_fit(const Events& ev, int M, const FitParams& o, float* mu, float* alpha,
-                      float* beta, double* ll, int* steps, int* status, int* counter,
-                      hipStream_t s) {
+                      float* beta, double* ll, int* steps, int* status, int* evals, float* ws,
+                      int64_t ws_floats, int* counter, hipStream_t s) {
   switch (lanes_for(M)) {
-    case 4: return launch_shared_fit<4>(ev, M, o, mu, alpha, beta, ll, steps, status, counter, s);
-    case 8: return launch_shared_fit<8>(ev, M, o, mu, alpha, beta, ll, steps, status, counter, s);
-    case 16: return launch_shared_fit<16>(ev, M, o, mu, alpha, beta, ll, steps, status, counter, s);
-    case 32: return launch_shared_fit<32>(ev, M, o, mu, alpha, beta, ll, steps, status, counter, s);
-    default: return launch_shared_fit<64>(ev, M, o, mu, alpha, beta, ll, steps, status, counter, s);
+    case 4: return launch_shared_fit<4>(ev, M, o, mu, alpha, beta, ll, steps, status, evals, ws, ws_floats, counter, s);
+    case 8: return launch_shared_fit<8>(ev, M, o, mu, alpha, beta, ll, steps, status, evals, ws, ws_floats, counter, s);
+    case 16: return launch_shared_fit<16>(ev, M, o, mu, alpha, beta, ll, steps, status, evals, ws, ws_floats, counter, s);
+    case 32: return launch_shared_fit<32>(ev, M, o, mu, alpha, beta, ll, steps, status, evals, ws, ws_floats, counter, s);
+    default: return launch_shared_fit<64>(ev, M, o, mu, alpha, beta, ll, steps, status, evals, ws, ws_floats, counter, s);
+  }
+}
+
+int64_t shared_lbfgs_workspace(int M, int64_t W) {
+  switch (lanes_for(M)) {
+    case 4: return shared_lbfgs_ws<4>(W);
+    case 8: return shared_lbfgs_ws<8>(W);
+    case 16: return shared_lbfgs_ws<16>(W);
+    case 32: return shared_lbfgs_ws<32>(W);
+    default: return shared_lbfgs_ws<64>(W);
   }
 }
 

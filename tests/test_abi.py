@@ -55,7 +55,7 @@ def test_host_error_paths():
     assert lib.mdhp_grad(None, None, None, None, None, None, None, None, None) == -1
     opts = _lib.MdhpFitOpts()
     assert lib.mdhp_fit_batch(None, ctypes.byref(opts), None, None, None, None, None, None,
-                              None) == -1
+                              None, None) == -1
     assert lib.mdhp_plan_windows(None) == 0
     lib.mdhp_plan_destroy(None)
 

@@ -328,3 +328,32 @@ def test_parameter_recovery(oracle_lib, synth_lib):
     zs = np.concatenate(zs)
     assert np.mean(np.abs(zs) <= 4.0) >= 0.95
     assert abs(np.mean(zs)) < 1.0
+
+
+def test_lbfgs_fit_reaches_lbfgsb_optimum(oracle_lib, synth_lib):
+    """The oracle's projected L-BFGS and scipy's L-BFGS-B (a library
+    implementation of bound-constrained quasi-Newton) agree on the optimum."""
+    from scipy.optimize import minimize
+    b = synth_lib.random_small(121, 3, 3, 0, n_lo=300, n_hi=600)
+    M = 3
+    for w in range(b.W):
+        s = b.subset([w])
+        N = s.n_events
+        mu0 = np.full((1, M), 0.3)
+        al0 = np.full((1, M, M), 0.1)
+        be0 = np.ones(1)
+        r = oracle_lib.fit(s.offsets, s.t, s.dim, s.T, M, mu0, al0, be0,
+                           oracle_lib.FitOpts(max_steps=3000, optimizer=2, ll_tol=1e-14))
+        assert r[5][0] in (0, 3)
+
+        def f(x):
+            ll, gm, ga, gb = oracle_lib.grad(s.offsets, s.t, s.dim, s.T, M, x[:M][None],
+                                             x[M:M + M * M].reshape(1, M, M), x[-1:], 0)
+            return -ll[0], -np.concatenate([gm[0], ga[0].ravel(), gb])
+        rate = N / s.T[0]
+        x0 = np.concatenate([mu0[0], al0[0].ravel(), be0])
+        ref = minimize(f, x0, jac=True, method="L-BFGS-B",
+                       bounds=[(1e-6 * rate, None)] * M + [(0, None)] * (M * M) + [(1e-3 * rate, None)],
+                       options=dict(maxiter=5000, ftol=1e-16, gtol=1e-12))
+        assert r[3][0] == pytest.approx(-ref.fun, rel=1e-8, abs=1e-8)
+        assert r[6][0] >= r[4][0] + 1
