@@ -1,0 +1,167 @@
+"""Training and evaluation pipeline of the learned warm start.
+
+1. Simulate training windows (seeded Ogata thinning) and fit each from the
+   cold start with the GPU solver; the fitted parameters are the targets.
+2. Compute the windows' count-histogram features on the GPU and train the
+   network (BF16 MFMA forward/backward, Adam) on z-scored log-parameters.
+3. On held-out windows, fit from the cold start and from the warm start
+   (network prediction, cold start kept where it is at least as likely)
+   with the same update rule and tolerance, and compare iterations and time.
+
+All numeric work runs in libmdhp.so; this module moves tensors and loops
+over mini-batches.
+"""
+
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+import synth
+
+from .api import BETA_SHARED, FIT_CONVERGED, FIT_STALLED, OPT_LBFGS, FitOptions, Plan
+from .surrogate import BINS, Surrogate, TargetStats, features, log_targets, warm_start
+
+DEFAULT_FIT = dict(max_steps=1000, optimizer=OPT_LBFGS, ll_tol=1e-7, history=8)
+
+
+def cold_start(b):
+    """mu_m = 0.5 max(N_m, 0.5) / T, beta = 1, alpha = 0.5 beta / M (branching ratio 0.5)."""
+    W, M = b.W, b.M
+    Nm = np.zeros((W, M))
+    wid = np.repeat(np.arange(W), b.counts)
+    np.add.at(Nm, (wid, b.dim), 1.0)
+    mu = (0.5 * np.maximum(Nm, 0.5) / b.T[:, None]).astype(np.float32)
+    beta = np.ones(W, np.float32)
+    alpha = np.full((W, M, M), 0.5 / M, np.float32)
+    return mu, alpha, beta
+
+
+@dataclass
+class DeviceBatch:
+    b: object
+    offsets: torch.Tensor
+    t: torch.Tensor
+    dim: torch.Tensor
+    T: torch.Tensor
+
+    @classmethod
+    def of(cls, b, device="cuda"):
+        return cls(b, torch.from_numpy(b.offsets).to(device), torch.from_numpy(b.t).to(device),
+                   torch.from_numpy(b.dim).to(device), torch.from_numpy(b.T).to(device))
+
+
+def make_batch(M: int, W: int, seed: int, first: int = 0):
+    if M == 16:
+        return synth.batch_m16(W=W, seed=seed, first=first)
+    if M == 64:
+        return synth.large_m64(W=W, seed=seed, first=first)
+    raise ValueError("warm-start workloads exist for M = 16 and M = 64")
+
+
+def fit_cold(db: DeviceBatch, opts: FitOptions):
+    b = db.b
+    plan = Plan(db.offsets, db.t, db.dim, db.T, b.M, BETA_SHARED)
+    mu0, al0, be0 = cold_start(b)
+    out = plan.fit(torch.from_numpy(mu0), torch.from_numpy(al0), torch.from_numpy(be0), opts,
+                   return_evals=True)
+    plan.close()
+    return out
+
+
+@dataclass
+class TrainingSet:
+    x: torch.Tensor          # BF16 features [N, M * BINS] on the device
+    y: np.ndarray            # log-parameter targets [N, M + M*M + 1]
+    ok: np.ndarray           # windows whose cold fit converged (used for training)
+    gen_s: float = 0.0       # simulation time (host)
+    fit_s: float = 0.0       # cold fits (GPU)
+    info: dict = field(default_factory=dict)
+
+
+def build_training_set(M: int, n_windows: int, seed: int = 1024, chunk: int = 4096,
+                       opts: FitOptions | None = None, log=None) -> TrainingSet:
+    opts = opts or FitOptions(**DEFAULT_FIT)
+    xs, ys, oks = [], [], []
+    gen_s = fit_s = 0.0
+    for first in range(0, n_windows, chunk):
+        W = min(chunk, n_windows - first)
+        t0 = time.perf_counter()
+        b = make_batch(M, W, seed, first)
+        t1 = time.perf_counter()
+        db = DeviceBatch.of(b)
+        mu, al, be, ll, st, stat, ev = fit_cold(db, opts)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        gen_s += t1 - t0
+        fit_s += t2 - t1
+        stat = stat.cpu().numpy()
+        xs.append(features(db.offsets, db.t, db.dim, db.T, M))
+        ys.append(log_targets(M, mu.cpu().numpy(), al.cpu().numpy(), be.cpu().numpy()))
+        oks.append((stat == FIT_CONVERGED) | (stat == FIT_STALLED))
+        if log:
+            log(f"training windows {first + W}/{n_windows}: sim {t1 - t0:.1f}s fit {t2 - t1:.2f}s")
+    return TrainingSet(torch.cat(xs), np.concatenate(ys), np.concatenate(oks), gen_s, fit_s)
+
+
+def train_surrogate(ts: TrainingSet, M: int, epochs: int = 20, lr: float = 1e-3,
+                    batch: int = 1024, seed: int = 1024, log=None):
+    keep = np.nonzero(ts.ok)[0]
+    stats = TargetStats.fit(ts.y[keep])
+    net = Surrogate(M, hidden=512, max_batch=batch, seed=seed)
+    x = ts.x[torch.from_numpy(keep).to(ts.x.device)]
+    y = torch.from_numpy(stats.normalize(ts.y[keep])).to(ts.x.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = net.train(x, y, epochs=epochs, lr=lr, batch=batch, seed=seed, log=log)
+    torch.cuda.synchronize()
+    net.stats = stats
+    return net, losses, time.perf_counter() - t0
+
+
+def warm_init(db: DeviceBatch, net: Surrogate, opts: FitOptions, plan: Plan | None = None):
+    """Features -> prediction -> warm start with fallback; returns the
+    initial parameters, the mask of windows that kept the warm start, and
+    the plan used."""
+    b = db.b
+    own = plan is None
+    plan = plan or Plan(db.offsets, db.t, db.dim, db.T, b.M, BETA_SHARED)
+    x = features(db.offsets, db.t, db.dim, db.T, b.M)
+    mu0, al0, be0 = cold_start(b)
+    mu, al, be, used = warm_start(plan, net, x, net.stats, mu0, al0, be0, opts)
+    if own:
+        return mu, al, be, used, plan
+    return mu, al, be, used, plan
+
+
+def compare(db: DeviceBatch, net: Surrogate, opts: FitOptions | None = None, repeats: int = 3):
+    """Cold vs warm fits of the same windows with the same rule: per-window
+    iterations and evaluations, and wall-clock per batch (mean of repeats)."""
+    opts = opts or FitOptions(**DEFAULT_FIT)
+    b = db.b
+    mu0, al0, be0 = (torch.from_numpy(v).to(db.t.device) for v in cold_start(b))
+    res = {}
+    for label in ("cold", "warm"):
+        times = []
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan = Plan(db.offsets, db.t, db.dim, db.T, b.M, BETA_SHARED)
+            if label == "warm":
+                mu, al, be, used, _ = warm_init(db, net, opts, plan)
+            else:
+                mu, al, be, used = mu0, al0, be0, None
+            out = plan.fit(mu, al, be, opts, return_evals=True)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            plan.close()
+        mu, al, be, ll, st, stat, ev = out
+        stat = stat.cpu().numpy()
+        res[label] = dict(seconds=float(np.mean(times)), steps=st.cpu().numpy(),
+                          evals=ev.cpu().numpy(), status=stat, ll=ll.cpu().numpy(),
+                          params=(mu.cpu().numpy(), al.cpu().numpy(), be.cpu().numpy()),
+                          used_warm=None if used is None else used.cpu().numpy())
+    return res
