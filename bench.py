@@ -59,12 +59,12 @@ def cold_start(b):
     return cs(b)
 
 
-def read_traffic(kernel: str):
+def read_traffic(kernel: str, source: str):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source."""
+    taken on the current kernel source (csrc/<source>)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.txt")
-    src = os.path.join(ROOT, "paper_2411_10258_amd", "csrc", "mdhp_shared.hip")
+    src = os.path.join(ROOT, "paper_2411_10258_amd", "csrc", source)
     if not (os.path.exists(path) and os.path.exists(src)):
         return None
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -109,9 +109,87 @@ def cpu_baseline(b, opts_kw, sample_windows: int, gpu_params=None):
     return out
 
 
+def bench_pair(args, dev) -> int:
+    """pair_m32: likelihood + gradient of 1,024 windows of 5,000 events, M = 32,
+    one decay per pair, at non-stationary parameters (one mdhp_grad launch per
+    step); the metric is event evaluations per second."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2411_10258_amd as mdhp
+
+    b = synth.pair_m32(W=1024 if args.windows == 4096 else args.windows, seed=2024)
+    g = np.random.default_rng(11)
+    mu = torch.from_numpy((b.mu * g.uniform(0.5, 1.5, b.mu.shape)).astype(np.float32)).to(dev)
+    al = torch.from_numpy((b.alpha * g.uniform(0.5, 1.5, b.alpha.shape)).astype(np.float32)).to(dev)
+    be = torch.from_numpy((b.beta * g.uniform(0.5, 1.5, b.beta.shape)).astype(np.float32)).to(dev)
+    plan = mdhp.Plan(b.offsets, b.t, b.dim, b.T, 32, mdhp.BETA_PAIR, device=dev)
+    ll = torch.empty(b.W, dtype=torch.float64, device=dev)
+    gm, ga, gb = torch.empty_like(mu), torch.empty_like(al), torch.empty_like(be)
+    for _ in range(args.warmup):
+        mdhp.mdhp_grad(plan.handle, mu, al, be, ll, gm, ga, gb)
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        e[0].record()
+        mdhp.mdhp_grad(plan.handle, mu, al, be, ll, gm, ga, gb)
+        e[1].record()
+        evs.append(e)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    k_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    M = 32
+    # Per event: two exponentials, the row read (4M: decay of R and S, alpha R,
+    # reduction), G_R and G_S rows (4M), the column update (5M), log/rcp.
+    flops = b.n_events * (16.0 * M + 8.0)
+    out = {
+        "metric": METRIC, "value": b.n_events / (ms * 1e-3), "unit": "event-evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (f64 per-window sums)", "data": "synthetic (Ogata thinning, seed 2024)",
+        "config": {"workload": f"pair_m32: {b.W} windows x 5000 events, M=32, one decay per "
+                               f"pair; likelihood + gradient (mdhp_grad) per step",
+                   "global_batch": b.W, "events": b.n_events, "parallelism": "none (1 GPU)"},
+        "grad_kernel_ms": k_ms,
+        "roofline": {"bound": "alu", "achieved": flops / (k_ms * 1e-3) / 1e12,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": flops / (k_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "pair_eval_kernel<32, true>", "flops_per_event_eval": 16.0 * M + 8.0,
+                     "event_evals_per_launch": float(b.n_events)},
+    }
+    if not args.no_cpu:
+        import oracle
+        s = b.subset(np.arange(8))
+        threads = min(16, os.cpu_count() or 1)
+        args_o = (s.offsets, s.t, s.dim, s.T, 32, mu[:8].cpu().numpy(), al[:8].cpu().numpy(),
+                  be[:8].cpu().numpy(), 1)
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < 5.0:
+            oracle.grad(*args_o, nthreads=threads)
+            reps += 1
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": reps * s.n_events / dt, "unit": "event-evals/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"likelihood+gradient of the first 8 windows "
+                                         f"({s.n_events} events), {reps} repetitions, {dt:.1f} s"}
+    plan.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["batch_m16", "large_m64", "pair_m32"],
+                    default="batch_m16",
+                    help="batch_m16: warm vs cold fits of 4,096 M=16 windows (default); "
+                         "large_m64: cold fits of 16,384 M=64 windows (~151M events); "
+                         "pair_m32: likelihood+gradient passes over 1,024 x 5,000 events "
+                         "with per-pair decays")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--windows", type=int, default=4096)
@@ -153,12 +231,25 @@ def main() -> int:
         print(json.dumps({"copy_bytes": src.numel() * 4}))
         return 0
 
+    if args.workload == "pair_m32":
+        return bench_pair(args, dev)
+    if args.workload == "large_m64":
+        args.no_warm = True
+        if args.windows == 4096:
+            args.windows = 16384
+        if args.cpu_sample == 96:
+            args.cpu_sample = 16
     opt = mdhp.OPT_LBFGS if args.optimizer == "lbfgs" else mdhp.OPT_PADAM
     opts_kw = dict(max_steps=args.max_steps, optimizer=opt, ll_tol=args.ll_tol, lr=args.lr)
     opts = mdhp.FitOptions(**opts_kw)
     log = lambda m: print(m, file=sys.stderr, flush=True)
 
-    b = synth.batch_m16(W=args.windows, seed=2024)
+    if args.workload == "large_m64":
+        t_gen = time.perf_counter()
+        b = synth.large_m64(W=args.windows, seed=2024)
+        log(f"generated {b.W} windows, {b.n_events} events in {time.perf_counter() - t_gen:.1f}s")
+    else:
+        b = synth.batch_m16(W=args.windows, seed=2024)
     db = warmstart.DeviceBatch.of(b, dev)
     mu0, al0, be0 = (torch.from_numpy(v).to(dev) for v in cold_start(b))
 
@@ -226,7 +317,12 @@ def main() -> int:
     ms = main_run["ms"]
     k_ms = main_run["kernel_ms"]
     achieved = evals * flops_per_event_eval(b.M) / (k_ms * 1e-3) / 1e12
-    kname = "shared_lbfgs_kernel_P16" if opt == mdhp.OPT_LBFGS else "shared_fit_kernel_P16"
+    if b.M <= 16:  # lane-major kernels (one window per wavefront)
+        kname = "lpc_lbfgs_kernel_MP16" if opt == mdhp.OPT_LBFGS else "lpc_fit_kernel_MP16"
+        ksrc = "mdhp_lpc.hip"
+    else:          # workgroup-per-window kernels
+        kname = "shared_lbfgs_kernel_P64" if opt == mdhp.OPT_LBFGS else "shared_fit_kernel_P64"
+        ksrc = "mdhp_shared.hip"
     out = {
         "metric": METRIC,
         "value": fits(main_run) / (ms * 1e-3),
@@ -239,9 +335,13 @@ def main() -> int:
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 (f64 per-window sums)",
-        "data": "synthetic (Ogata thinning, seed 2024; network trained on seed 1024)",
-        "config": {"workload": f"batch_m16: {b.W} windows, M=16, shared decay, log-normal "
-                               f"counts median 1000 clipped [100, 20000], {b.n_events} events; "
+        "data": "synthetic (Ogata thinning, seed 2024" + ("; network trained on seed 1024)"
+                                                           if warm is not None else ")"),
+        "config": {"workload": (f"batch_m16: {b.W} windows, M=16, shared decay, log-normal "
+                                f"counts median 1000 clipped [100, 20000], {b.n_events} events; "
+                                if b.M == 16 else
+                                f"large_m64: {b.W} windows, M=64, shared decay, log-normal "
+                                f"counts median 5000 clipped [500, 50000], {b.n_events} events; ") +
                                f"{'warm' if warm else 'cold'} start, projected "
                                f"{args.optimizer}, <= {args.max_steps} updates, "
                                f"ll_tol {args.ll_tol}",
@@ -257,7 +357,7 @@ def main() -> int:
         "fit_kernel_ms": k_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": read_traffic(kname),
+                     "traffic": read_traffic(kname, ksrc),
                      "hbm_algorithmic_GBs": evals * BYTES_PER_EVENT_EVAL / (k_ms * 1e-3) / 1e9,
                      "kernel": kname, "flops_per_event_eval": flops_per_event_eval(b.M),
                      "event_evals_per_launch": evals},

@@ -13,6 +13,8 @@
 struct mdhp_plan {
   int64_t W = 0, N = 0;
   int32_t M = 0, beta_mode = 0;
+  bool lane_major = false;  // events stored lane-major per window (M <= 16, one decay)
+  int64_t slots = 0;        // length of dt / d
   float* dt = nullptr;
   uint8_t* d = nullptr;
   int64_t* begin = nullptr;
@@ -20,6 +22,7 @@ struct mdhp_plan {
   double* T = nullptr;
   float* end_gap = nullptr;
   int32_t* order = nullptr;
+  int32_t* counts = nullptr;  // [W][M] events per dimension (lane-major plans)
   int* counter = nullptr;  // window queue head
   int* flags = nullptr;    // [0] error bits of prepare / check_params
   double* ll_ws = nullptr; // [2 W] likelihoods of the warm and cold starts
@@ -58,14 +61,24 @@ mdhp_status hip_fail(hipError_t e, const char* where) { return mdhp_hip_fail(e, 
 
 // Sec. IV-B "Stage 1" counterpart: per event, the gap to the previous event
 // of the same window in FP64 (stored FP32; a positive gap never rounds to 0),
-// the u8 dimension id, and validation of order and domain.
+// the u8 dimension id, and validation of order and domain.  With slot_begin
+// the window's events go lane-major: event k of a window of n events lands
+// in slot slot_begin[w] + 64 (k mod c) + k / c, c = ceil(n / 64), so that
+// lane l's chunk (events l c .. l c + c - 1) is read 64 lanes at a time.
 __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double* __restrict__ t,
                                const int32_t* __restrict__ dim, const double* __restrict__ T,
-                               int64_t W, int M, float* __restrict__ dt,
-                               uint8_t* __restrict__ d8, float* __restrict__ end_gap,
-                               double* __restrict__ Tc, int* flags) {
+                               const int64_t* __restrict__ slot_begin, int64_t W, int M,
+                               float* __restrict__ dt, uint8_t* __restrict__ d8,
+                               float* __restrict__ end_gap, double* __restrict__ Tc,
+                               int32_t* __restrict__ counts, int* flags) {
+  __shared__ int cnt[MDHP_MAX_M];
   for (int64_t w = blockIdx.x; w < W; w += gridDim.x) {
+    if (counts) {
+      for (int m = threadIdx.x; m < M; m += blockDim.x) cnt[m] = 0;
+      __syncthreads();
+    }
     const int64_t b = offsets[w], e = offsets[w + 1];
+    const int64_t c = (e - b + 63) / 64;
     const double Tw = T[w];
     int err = 0;
     if (!(Tw > 0.0) || !isfinite(Tw)) err |= kErrDomain;
@@ -78,8 +91,16 @@ __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double
       if (di < 0 || di >= M) err |= kErrDomain;
       float g = (float)(ti - prev);
       if (ti > prev && !(g > 0.f)) g = 1.17549435e-38f;
-      dt[i] = g > 0.f ? g : 0.f;
-      d8[i] = (uint8_t)(di < 0 ? 0 : (di >= M ? 0 : di));
+      const int64_t k = i - b;
+      const int64_t dst = slot_begin ? slot_begin[w] + 64 * (k % c) + k / c : i;
+      dt[dst] = g > 0.f ? g : 0.f;
+      d8[dst] = (uint8_t)(di < 0 ? 0 : (di >= M ? 0 : di));
+      if (counts && di >= 0 && di < M) atomicAdd(&cnt[di], 1);
+    }
+    if (counts) {
+      __syncthreads();
+      for (int m = threadIdx.x; m < M; m += blockDim.x) counts[w * M + m] = cnt[m];
+      __syncthreads();
     }
     if (threadIdx.x == 0) {
       const double last = e > b ? t[e - 1] : 0.0;
@@ -108,8 +129,23 @@ __global__ void zero_int_kernel(int* p) { *p = 0; }
 
 bool plan_ok(const mdhp_plan* p) { return p && p->magic == kMagic; }
 
+Events events_of(const mdhp_plan* p);
+
+// Likelihood (and gradient if g_mu) of every window: per-pair, lane-major
+// (M <= 16) or workgroup (M > 16) kernels, as the plan was laid out.
+hipError_t eval_plan(const mdhp_plan* p, const float* mu, const float* alpha, const float* beta,
+                     double* ll, float* g_mu, float* g_alpha, float* g_beta, hipStream_t s) {
+  const Events ev = events_of(p);
+  const bool grad = g_mu != nullptr;
+  if (p->beta_mode == MDHP_BETA_PAIR)
+    return pair_eval(ev, p->M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, p->counter, s, grad);
+  if (p->lane_major)
+    return lpc_eval(ev, p->M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, p->counter, s, grad);
+  return shared_eval(ev, p->M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, p->counter, s, grad);
+}
+
 Events events_of(const mdhp_plan* p) {
-  return Events{p->W, p->dt, p->d, p->begin, p->n, p->T, p->end_gap, p->order};
+  return Events{p->W, p->dt, p->d, p->begin, p->n, p->T, p->end_gap, p->order, p->counts};
 }
 
 template <class T>
@@ -128,6 +164,7 @@ void free_plan(mdhp_plan* p) {
   (void)hipFree(p->T);
   (void)hipFree(p->end_gap);
   (void)hipFree(p->order);
+  (void)hipFree(p->counts);
   (void)hipFree(p->counter);
   (void)hipFree(p->flags);
   (void)hipFree(p->ll_ws);
@@ -199,16 +236,34 @@ mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, 
   p->beta_mode = beta_mode;
   p->magic = kMagic;
   const int64_t N = b->n_events;
-  if ((e = dev_alloc(&p->dt, N)) != hipSuccess || (e = dev_alloc(&p->d, N)) != hipSuccess ||
+  // Lane-major slots: 64 ceil(n_w / 64) per window.
+  p->lane_major = beta_mode == MDHP_BETA_SHARED && M <= kLaneMajorMaxM;
+  std::vector<int64_t> sbeg;
+  if (p->lane_major) {
+    sbeg.resize(W);
+    int64_t acc = 0;
+    for (int64_t w = 0; w < W; ++w) {
+      sbeg[w] = acc;
+      acc += 64 * ((off[w + 1] - off[w] + 63) / 64);
+    }
+    p->slots = acc;
+  } else {
+    p->slots = N;
+  }
+  const int64_t fit_ws = beta_mode != MDHP_BETA_SHARED ? 0
+                         : p->lane_major             ? lpc_lbfgs_workspace(M, W)
+                                                     : shared_lbfgs_workspace(M, W);
+  if ((e = dev_alloc(&p->dt, p->slots)) != hipSuccess ||
+      (e = dev_alloc(&p->d, p->slots)) != hipSuccess ||
       (e = dev_alloc(&p->begin, W)) != hipSuccess || (e = dev_alloc(&p->n, W)) != hipSuccess ||
       (e = dev_alloc(&p->T, W)) != hipSuccess || (e = dev_alloc(&p->end_gap, W)) != hipSuccess ||
       (e = dev_alloc(&p->order, W)) != hipSuccess ||
+      (p->lane_major && (e = dev_alloc(&p->counts, W * M)) != hipSuccess) ||
       (e = dev_alloc(&p->counter, 1)) != hipSuccess ||
       (e = dev_alloc(&p->flags, 1)) != hipSuccess ||
       (e = dev_alloc(&p->ll_ws, 2 * W)) != hipSuccess ||
-      (beta_mode == MDHP_BETA_SHARED &&
-       (e = dev_alloc(&p->fit_ws, (size_t)(p->fit_ws_floats = shared_lbfgs_workspace(M, W)))) !=
-           hipSuccess)) {
+      (fit_ws > 0 && (e = dev_alloc(&p->fit_ws, (size_t)(p->fit_ws_floats = fit_ws))) !=
+                         hipSuccess)) {
     free_plan(p);
     return hip_fail(e, "plan_create: allocation");
   }
@@ -220,8 +275,13 @@ mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, 
                    [&](int32_t a, int32_t c) { return cnt[a] > cnt[c]; });
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, p->flags);
   e = hipGetLastError();
+  if (e == hipSuccess && p->lane_major && p->slots > 0) {  // padding slots: gap 0, no dimension
+    e = hipMemsetAsync(p->dt, 0, p->slots * sizeof(float), s);
+    if (e == hipSuccess) e = hipMemsetAsync(p->d, 0xFF, p->slots, s);
+  }
   if (e == hipSuccess && W > 0) {
-    e = hipMemcpyAsync(p->begin, off.data(), W * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(p->begin, p->lane_major ? sbeg.data() : off.data(), W * sizeof(int64_t),
+                       hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(p->n, cnt.data(), W * sizeof(int32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -229,7 +289,8 @@ mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, 
     if (e == hipSuccess) {
       const int grid = (int)std::min<int64_t>(W, 65536);
       hipLaunchKernelGGL(prepare_kernel, dim3(grid), dim3(256), 0, s, b->offsets, b->t, b->dim,
-                         b->T, W, M, p->dt, p->d, p->end_gap, p->T, p->flags);
+                         b->T, p->lane_major ? p->begin : nullptr, W, M, p->dt, p->d,
+                         p->end_gap, p->T, p->counts, p->flags);
       e = hipGetLastError();
     }
   }
@@ -267,13 +328,8 @@ mdhp_status mdhp_loglik(mdhp_plan* p, const float* mu, const float* alpha, const
   if (!plan_ok(p)) return fail(MDHP_E_INVAL, "loglik: invalid plan");
   if (p->W > 0 && (!mu || !alpha || !beta || !ll))
     return fail(MDHP_E_INVAL, "loglik: null pointer");
-  hipStream_t s = (hipStream_t)stream;
-  const Events ev = events_of(p);
-  hipError_t e = p->beta_mode == MDHP_BETA_SHARED
-                     ? shared_eval(ev, p->M, mu, alpha, beta, ll, nullptr, nullptr, nullptr,
-                                   p->counter, s, false)
-                     : pair_eval(ev, p->M, mu, alpha, beta, ll, nullptr, nullptr, nullptr,
-                                 p->counter, s, false);
+  const hipError_t e = eval_plan(p, mu, alpha, beta, ll, nullptr, nullptr, nullptr,
+                                 (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "loglik: launch");
   return MDHP_OK;
 }
@@ -283,13 +339,8 @@ mdhp_status mdhp_grad(mdhp_plan* p, const float* mu, const float* alpha, const f
   if (!plan_ok(p)) return fail(MDHP_E_INVAL, "grad: invalid plan");
   if (p->W > 0 && (!mu || !alpha || !beta || !ll || !g_mu || !g_alpha || !g_beta))
     return fail(MDHP_E_INVAL, "grad: null pointer");
-  hipStream_t s = (hipStream_t)stream;
-  const Events ev = events_of(p);
-  hipError_t e = p->beta_mode == MDHP_BETA_SHARED
-                     ? shared_eval(ev, p->M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta,
-                                   p->counter, s, true)
-                     : pair_eval(ev, p->M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta,
-                                 p->counter, s, true);
+  const hipError_t e = eval_plan(p, mu, alpha, beta, ll, g_mu, g_alpha, g_beta,
+                                 (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "grad: launch");
   return MDHP_OK;
 }
@@ -318,11 +369,13 @@ mdhp_status mdhp_fit_batch(mdhp_plan* p, const mdhp_fit_opts* o, float* mu, floa
                o->adam_b1,    o->adam_b2,        o->adam_eps};
   hipStream_t s = (hipStream_t)stream;
   const Events ev = events_of(p);
-  hipError_t e = p->beta_mode == MDHP_BETA_SHARED
-                     ? shared_fit(ev, p->M, fp, mu, alpha, beta, ll, steps, status, evals,
-                                  p->fit_ws, p->fit_ws_floats, p->counter, s)
-                     : pair_fit(ev, p->M, fp, mu, alpha, beta, ll, steps, status, evals,
-                                p->counter, s);
+  hipError_t e =
+      p->beta_mode == MDHP_BETA_PAIR
+          ? pair_fit(ev, p->M, fp, mu, alpha, beta, ll, steps, status, evals, p->counter, s)
+      : p->lane_major ? lpc_fit(ev, p->M, fp, mu, alpha, beta, ll, steps, status, evals,
+                                p->fit_ws, p->fit_ws_floats, p->counter, s)
+                      : shared_fit(ev, p->M, fp, mu, alpha, beta, ll, steps, status, evals,
+                                   p->fit_ws, p->fit_ws_floats, p->counter, s);
   if (e != hipSuccess) return hip_fail(e, "fit_batch: launch");
   return MDHP_OK;
 }
@@ -340,17 +393,13 @@ mdhp_status mdhp_warm_start(mdhp_plan* p, const float* pred, const float* mean,
       !beta || !used_warm)
     return fail(MDHP_E_INVAL, "warm_start: null pointer");
   hipStream_t s = (hipStream_t)stream;
-  const Events ev = events_of(p);
   double* ll_w = p->ll_ws;
   double* ll_c = p->ll_ws + p->W;
   hipError_t e = warm_params(pred, mean, stdv, p->n, p->T, p->W, p->M, (float)o->mu_floor_rel,
                              (float)o->beta_floor_rel, mu, alpha, beta, s);
+  if (e == hipSuccess) e = eval_plan(p, mu, alpha, beta, ll_w, nullptr, nullptr, nullptr, s);
   if (e == hipSuccess)
-    e = shared_eval(ev, p->M, mu, alpha, beta, ll_w, nullptr, nullptr, nullptr, p->counter, s,
-                    false);
-  if (e == hipSuccess)
-    e = shared_eval(ev, p->M, mu_cold, alpha_cold, beta_cold, ll_c, nullptr, nullptr, nullptr,
-                    p->counter, s, false);
+    e = eval_plan(p, mu_cold, alpha_cold, beta_cold, ll_c, nullptr, nullptr, nullptr, s);
   if (e == hipSuccess)
     e = choose_init(ll_w, ll_c, p->W, p->M, mu_cold, alpha_cold, beta_cold, mu, alpha, beta,
                     used_warm, s);

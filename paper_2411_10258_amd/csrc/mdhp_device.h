@@ -50,13 +50,47 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// Inclusive prefix sum over the P lanes of a group (lane order).
+// v from lane - K of the same 16-lane row, 0 where that lane is outside the
+// row (DPP row_shr with bound_ctrl).
+template <int K>
+__device__ __forceinline__ float row_shr(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                0x110 + K, 0xF, 0xF, true));
+}
+
+// Inclusive prefix sum over the P lanes of a group (lane order).  Within
+// 16-lane rows by DPP shifts; groups wider than a row add the earlier rows'
+// totals read across lanes.
 template <int P>
 __device__ __forceinline__ float group_scan(float v, int lane) {
-#pragma unroll
-  for (int k = 1; k < P; k <<= 1) {
-    const float y = __shfl_up(v, k, P);
-    if (lane >= k) v += y;
+  constexpr int R = P < 16 ? P : 16;
+  const int lr = lane & (R - 1);
+  float y;
+  y = row_shr<1>(v);
+  if (R > 1 && lr >= 1) v += y;
+  if constexpr (R > 2) {
+    y = row_shr<2>(v);
+    if (lr >= 2) v += y;
+  }
+  if constexpr (R > 4) {
+    y = row_shr<4>(v);
+    if (lr >= 4) v += y;
+  }
+  if constexpr (R > 8) {
+    y = row_shr<8>(v);
+    if (lr >= 8) v += y;
+  }
+  if constexpr (P > 16) {
+    // Add the totals of the earlier 16-lane rows of the group.
+    const int row = lane >> 4;
+    const float t0 = __shfl(v, (threadIdx.x & ~(P - 1) & 63) + 15, 64);
+    float add = row >= 1 ? t0 : 0.f;
+    if constexpr (P > 32) {
+      const float t1 = __shfl(v, (threadIdx.x & ~(P - 1) & 63) + 31, 64);
+      const float t2 = __shfl(v, (threadIdx.x & ~(P - 1) & 63) + 47, 64);
+      add += (row >= 2 ? t1 : 0.f) + (row >= 3 ? t2 : 0.f);
+    }
+    v += add;
   }
   return v;
 }

@@ -12,6 +12,11 @@
 namespace mdhp {
 
 constexpr int kBlock = 256;  // threads per workgroup (4 waves of 64)
+#ifndef MDHP_MIN_BLOCKS
+#define MDHP_MIN_BLOCKS 1
+#endif
+// Workgroups per CU the fit kernels are compiled for (register budget).
+constexpr int kMinBlocks = MDHP_MIN_BLOCKS;
 constexpr int kMaxHistory = 16;  // largest L-BFGS memory
 
 // FP64 G_R accumulators each thread owns for a P x P matrix.
@@ -29,11 +34,12 @@ struct Events {
   int64_t W;
   const float* dt;       // gap to the previous event of the window (the first: t_0), FP64-computed
   const uint8_t* d;      // dimension ids
-  const int64_t* begin;  // [W] first event of each window
+  const int64_t* begin;  // [W] first event (compact) or first slot (lane-major) of each window
   const int32_t* n;      // [W] events per window
   const double* T;       // [W] window lengths
   const float* end_gap;  // [W] T - t_last (T for an empty window), FP64-computed
   const int32_t* order;  // [W] window ids, largest first
+  const int32_t* counts; // [W][M] events per dimension (lane-major plans only, else null)
 };
 
 // Fit options as the kernels read them.
@@ -62,6 +68,22 @@ inline void reset_counter(int* counter, hipStream_t s) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
 }
 
+#ifndef MDHP_LANE_MAJOR_MAX_M
+#define MDHP_LANE_MAJOR_MAX_M 16
+#endif
+// Largest M whose shared-decay plans use the lane-major layout and kernels.
+constexpr int kLaneMajorMaxM = MDHP_LANE_MAJOR_MAX_M;
+
+// Lane-major (one chunk per lane, one window per wave) kernels, M <= 16.
+hipError_t lpc_eval(const Events& ev, int M, const float* mu, const float* alpha,
+                    const float* beta, double* ll, float* g_mu, float* g_alpha, float* g_beta,
+                    int* counter, hipStream_t s, bool grad);
+hipError_t lpc_fit(const Events& ev, int M, const FitParams& o, float* mu, float* alpha,
+                   float* beta, double* ll, int* steps, int* status, int* evals, float* ws,
+                   int64_t ws_floats, int* counter, hipStream_t s);
+int64_t lpc_lbfgs_workspace(int M, int64_t W);
+
+// Workgroup-per-window kernels for the compact layout, 16 < M <= 64.
 hipError_t shared_eval(const Events& ev, int M, const float* mu, const float* alpha,
                        const float* beta, double* ll, float* g_mu, float* g_alpha, float* g_beta,
                        int* counter, hipStream_t s, bool grad);

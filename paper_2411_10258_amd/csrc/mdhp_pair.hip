@@ -88,7 +88,7 @@ __device__ __forceinline__ void column_update(PairLds<P>& sh, float* Rs, float* 
 // Evaluates one window with parameters in LDS.  Results: sh.scal[0] = ll;
 // if GRAD also sh.gR / sh.gS (FP32 sums), sh.Cmn, sh.Fmn, sh.gmu.
 template <int P, bool GRAD>
-__device__ void eval_window_pair(PairLds<P>& sh, const float* __restrict__ dtg,
+__device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, const float* __restrict__ dtg,
                                  const uint8_t* __restrict__ dg, int64_t begin, int n, double T,
                                  float end_gap, int M) {
   using C = PairCfg<P>;

@@ -67,7 +67,7 @@ struct SharedLds {
 // G_R[e] for e = tid + k * kBlock (FP64), sh.Cn, sh.Fn, sh.gmu (= d ll/d mu),
 // sh.scal[1] = d ll / d beta.
 template <int P, bool GRAD>
-__device__ void eval_window(SharedLds<P>& sh, const float* __restrict__ dtg,
+__device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __restrict__ dtg,
                             const uint8_t* __restrict__ dg, int64_t begin, int n, double T,
                             float end_gap, int M, double (&gR64)[own_count(P)]) {
   constexpr int G = SharedLds<P>::G;
@@ -111,7 +111,8 @@ __device__ void eval_window(SharedLds<P>& sh, const float* __restrict__ dtg,
         dt_n = jr < len ? dtw[j0 + jr] : 0.f;
         d_n = jr < len ? (int)dw[j0 + jr] : 0;
       }
-      float prev = __shfl_up(dt, 1, P);  // gap of the next event (exclusive scan input)
+      // Gap of the next event (the exclusive scan's input).
+      float prev = P <= 16 ? row_shr<1>(dt) : __shfl_up(dt, 1, P);
       prev = lane == 0 ? 0.f : prev;
       const float tau = later + group_scan<P>(prev, lane);
       if (valid) {
@@ -180,7 +181,7 @@ __device__ void eval_window(SharedLds<P>& sh, const float* __restrict__ dtg,
         d_n = jl < len ? (int)dw[j0 + jl] : 0;
       }
       const float a_l = __expf(-beta * dt_l);
-      float Rj[B], Sj[B], Lj[B];
+      float Rj[B], ASj[B], Lj[B];  // R(j), alpha_{d_j n} S_n(j), alpha_{d_j n} R_n(j)
       int Dj[B];
       static_for<B>([&](auto J) {
         constexpr int j = decltype(J)::value;
@@ -192,10 +193,11 @@ __device__ void eval_window(SharedLds<P>& sh, const float* __restrict__ dtg,
         R = a * X;
         S = fmaf(a, S, dt * R);
         Pn = f ? 0.f : Pn;
+        const float al = sh.alpha[d * P + lane];
         Rj[j] = R;
-        Sj[j] = S;
+        ASj[j] = al * S;
         Dj[j] = d;
-        Lj[j] = sh.alpha[d * P + lane] * R;
+        Lj[j] = al * R;
         const bool mine = j < nvalid && d == lane;
         Pn += mine ? 1.f : 0.f;
         cnt += mine ? 1 : 0;
@@ -218,7 +220,7 @@ __device__ void eval_window(SharedLds<P>& sh, const float* __restrict__ dtg,
           constexpr int j = decltype(J)::value;
           const float w = group_bcast<P, j>(wk);  // zero for events past the chunk end
           atomicAdd(&gRc[Dj[j] * P + lane], w * Rj[j]);
-          gbp = fmaf(w * sh.alpha[Dj[j] * P + lane], Sj[j], gbp);
+          gbp = fmaf(w, ASj[j], gbp);
           gmup += Dj[j] == lane ? w : 0.f;
         });
       }
@@ -329,7 +331,7 @@ __device__ int next_window(SharedLds<P>& sh, int* counter, int first) {
 }
 
 template <int P, bool GRAD>
-__global__ __launch_bounds__(kBlock) void shared_eval_kernel(Events ev, int M, const float* mu,
+__global__ __launch_bounds__(kBlock, kMinBlocks) void shared_eval_kernel(Events ev, int M, const float* mu,
                                                              const float* alpha,
                                                              const float* beta, double* ll,
                                                              float* g_mu, float* g_alpha,
@@ -361,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void shared_eval_kernel(Events ev, int M, c
 
 // Persistent projected-gradient fit (see mdhp_fit_opts for the rule).
 template <int P>
-__global__ __launch_bounds__(kBlock) void shared_fit_kernel(Events ev, int M, FitParams o,
+__global__ __launch_bounds__(kBlock, kMinBlocks) void shared_fit_kernel(Events ev, int M, FitParams o,
                                                             float* mu, float* alpha, float* beta,
                                                             double* ll, int* steps, int* status,
                                                             int* evals_out, int* counter) {
@@ -501,7 +503,7 @@ __device__ __forceinline__ double block_max_abs(double v, double* scratch) {
 // reads and writes; the scalars of the two-loop recursion come from block
 // reductions.
 template <int P>
-__global__ __launch_bounds__(kBlock) void shared_lbfgs_kernel(Events ev, int M, FitParams o,
+__global__ __launch_bounds__(kBlock, kMinBlocks) void shared_lbfgs_kernel(Events ev, int M, FitParams o,
                                                               float* mu, float* alpha,
                                                               float* beta, double* ll,
                                                               int* steps, int* status,

@@ -60,7 +60,12 @@ def test_lbfgs_semantics(gpu, oracle_lib, synth_lib):
     l0 = oracle_lib.loglik(b.offsets, b.t, b.dim, b.T, b.M, mu0, al0, be0, 0)
     ls, *_ = oracle_lib.scales(b.offsets, b.t, b.dim, b.T, b.M, mu0, al0, be0, 0)
     assert ll_errors(ll.cpu().numpy(), l0, ls).max() <= LL_TOL
-    o = gpu.FitOptions(max_steps=30, optimizer=gpu.OPT_LBFGS, fix_beta=True, history=3,
+    # 8 updates: far enough to exercise the history ring (memory 3) and the
+    # bounds, early enough that the iterates are still comparable across
+    # precisions -- a 1e-6 relative perturbation of mu0 moves the oracle's own
+    # 8-update ll by at most ~5e-6 relative on these windows, but its 30-update
+    # ll by up to ~4e-3 (L-BFGS with a short memory amplifies rounding).
+    o = gpu.FitOptions(max_steps=8, optimizer=gpu.OPT_LBFGS, fix_beta=True, history=3,
                        ll_tol=0.0)
     mu, al, be, ll, st, stat = plan.fit(torch.from_numpy(mu0), torch.from_numpy(al0),
                                         torch.from_numpy(be0), o)
@@ -70,11 +75,12 @@ def test_lbfgs_semantics(gpu, oracle_lib, synth_lib):
     assert np.all(mu.cpu().numpy() >= 1e-6 * rate[:, None] * (1 - 1e-6))
     # Same rule in FP64 lands on the same likelihood level.
     r = oracle_lib.fit(b.offsets, b.t, b.dim, b.T, b.M, mu0, al0, be0,
-                       oracle_lib.FitOpts(max_steps=30, optimizer=2, fix_beta=1, history=3,
+                       oracle_lib.FitOpts(max_steps=8, optimizer=2, fix_beta=1, history=3,
                                           ll_tol=0.0))
     l_gpu = oracle_lib.loglik(b.offsets, b.t, b.dim, b.T, b.M, mu.cpu().numpy(),
                               al.cpu().numpy(), be.cpu().numpy(), 0)
-    assert np.all(np.abs(l_gpu - r[3]) <= 1e-3 * np.abs(r[3]))
+    assert np.all(l_gpu > l0)
+    assert np.all(np.abs(l_gpu - r[3]) <= 2e-4 * np.abs(r[3]))
     with pytest.raises(gpu.MdhpError):
         plan.fit(torch.from_numpy(mu0), torch.from_numpy(al0), torch.from_numpy(be0),
                  gpu.FitOptions(optimizer=gpu.OPT_LBFGS, history=17))

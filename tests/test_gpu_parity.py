@@ -62,6 +62,26 @@ def test_ties_shared(gpu, oracle_lib, synth_lib, M):
     _check_grad(gpu, oracle_lib, b, mu, alpha, beta, f"ties shared M={M}")
 
 
+@pytest.mark.parametrize("M,tie_grid", [(5, 0.0), (16, 0.0), (16, 0.5)])
+def test_chunk_boundaries_shared(gpu, oracle_lib, synth_lib, M, tie_grid):
+    # Window sizes at and around multiples of 64 (one chunk per lane), with
+    # and without ties.
+    counts = np.array([0, 1, 2, 63, 64, 65, 127, 128, 129, 640, 641, 4095, 4096, 4097])
+    W = len(counts)
+    g = np.random.default_rng(40 + M)
+    mu = g.uniform(0.2, 1.0, (W, M))
+    alpha = g.uniform(0.0, 0.5 / M, (W, M, M))
+    beta = g.uniform(0.5, 2.5, W)
+    off, t, d, T = synth_lib.simulate(M, 0, mu, alpha, beta, counts=counts, seed=40 + M,
+                                      nthreads=1)
+    if tie_grid > 0:
+        t = np.floor(t / tie_grid) * tie_grid
+        T = np.maximum(T, tie_grid)
+    b = synth_lib.Batch(M, 0, off, t, d, T, mu, alpha, beta)
+    th = _random_theta(b, M)
+    _check_grad(gpu, oracle_lib, b, *th, f"chunk boundaries M={M} grid={tie_grid}")
+
+
 def test_all_events_tied(gpu, oracle_lib, synth_lib):
     # One window whose 3,000 events all share one time, one with an event at T.
     M = 3
