@@ -23,7 +23,8 @@ struct mdhp_plan {
   float* end_gap = nullptr;
   int32_t* order = nullptr;
   int32_t* counts = nullptr;  // [W][M] events per dimension (lane-major plans)
-  int* counter = nullptr;  // window queue head
+  int* counter = nullptr;  // window queue heads [2]
+  int64_t n_big = 0;       // lane-major: windows run by a whole workgroup
   int* flags = nullptr;    // [0] error bits of prepare / check_params
   double* ll_ws = nullptr; // [2 W] likelihoods of the warm and cold starts
   float* fit_ws = nullptr; // L-BFGS per-workgroup vectors
@@ -33,7 +34,10 @@ struct mdhp_plan {
 
 namespace mdhp {
 
-__global__ void reset_counter_kernel(int* counter) { *counter = 0; }
+__global__ void reset_counter_kernel(int* counter) {
+  counter[0] = 0;
+  counter[1] = 0;
+}
 
 namespace {
 thread_local std::string g_last_msg;
@@ -63,8 +67,9 @@ mdhp_status hip_fail(hipError_t e, const char* where) { return mdhp_hip_fail(e, 
 // of the same window in FP64 (stored FP32; a positive gap never rounds to 0),
 // the u8 dimension id, and validation of order and domain.  With slot_begin
 // the window's events go lane-major: event k of a window of n events lands
-// in slot slot_begin[w] + 64 (k mod c) + k / c, c = ceil(n / 64), so that
-// lane l's chunk (events l c .. l c + c - 1) is read 64 lanes at a time.
+// in slot slot_begin[w] + L (k mod c) + k / c, with L = lane_team(n) chunks
+// and c = ceil(n / L), so that chunk l (events l c .. l c + c - 1) is read
+// a wave at a time.
 __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double* __restrict__ t,
                                const int32_t* __restrict__ dim, const double* __restrict__ T,
                                const int64_t* __restrict__ slot_begin, int64_t W, int M,
@@ -78,7 +83,8 @@ __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double
       __syncthreads();
     }
     const int64_t b = offsets[w], e = offsets[w + 1];
-    const int64_t c = (e - b + 63) / 64;
+    const int64_t L = lane_team(e - b);
+    const int64_t c = (e - b + L - 1) / L;
     const double Tw = T[w];
     int err = 0;
     if (!(Tw > 0.0) || !isfinite(Tw)) err |= kErrDomain;
@@ -92,7 +98,7 @@ __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double
       float g = (float)(ti - prev);
       if (ti > prev && !(g > 0.f)) g = 1.17549435e-38f;
       const int64_t k = i - b;
-      const int64_t dst = slot_begin ? slot_begin[w] + 64 * (k % c) + k / c : i;
+      const int64_t dst = slot_begin ? slot_begin[w] + L * (k % c) + k / c : i;
       dt[dst] = g > 0.f ? g : 0.f;
       d8[dst] = (uint8_t)(di < 0 ? 0 : (di >= M ? 0 : di));
       if (counts && di >= 0 && di < M) atomicAdd(&cnt[di], 1);
@@ -145,7 +151,8 @@ hipError_t eval_plan(const mdhp_plan* p, const float* mu, const float* alpha, co
 }
 
 Events events_of(const mdhp_plan* p) {
-  return Events{p->W, p->dt, p->d, p->begin, p->n, p->T, p->end_gap, p->order, p->counts};
+  return Events{p->W,     p->dt,      p->d,     p->begin,  p->n,
+                p->T,     p->end_gap, p->order, p->counts, p->n_big};
 }
 
 template <class T>
@@ -236,22 +243,24 @@ mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, 
   p->beta_mode = beta_mode;
   p->magic = kMagic;
   const int64_t N = b->n_events;
-  // Lane-major slots: 64 ceil(n_w / 64) per window.
+  // Lane-major slots: L ceil(n_w / L) per window, L = lane_team(n_w).
   p->lane_major = beta_mode == MDHP_BETA_SHARED && M <= kLaneMajorMaxM;
   std::vector<int64_t> sbeg;
   if (p->lane_major) {
     sbeg.resize(W);
     int64_t acc = 0;
     for (int64_t w = 0; w < W; ++w) {
+      const int64_t n = off[w + 1] - off[w], L = lane_team(n);
       sbeg[w] = acc;
-      acc += 64 * ((off[w + 1] - off[w] + 63) / 64);
+      acc += L * ((n + L - 1) / L);
+      if (n >= kBigWindow) ++p->n_big;
     }
     p->slots = acc;
   } else {
     p->slots = N;
   }
   const int64_t fit_ws = beta_mode != MDHP_BETA_SHARED ? 0
-                         : p->lane_major             ? lpc_lbfgs_workspace(M, W)
+                         : p->lane_major             ? lpc_lbfgs_workspace(M, W, p->n_big)
                                                      : shared_lbfgs_workspace(M, W);
   if ((e = dev_alloc(&p->dt, p->slots)) != hipSuccess ||
       (e = dev_alloc(&p->d, p->slots)) != hipSuccess ||
@@ -259,7 +268,7 @@ mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, 
       (e = dev_alloc(&p->T, W)) != hipSuccess || (e = dev_alloc(&p->end_gap, W)) != hipSuccess ||
       (e = dev_alloc(&p->order, W)) != hipSuccess ||
       (p->lane_major && (e = dev_alloc(&p->counts, W * M)) != hipSuccess) ||
-      (e = dev_alloc(&p->counter, 1)) != hipSuccess ||
+      (e = dev_alloc(&p->counter, 2)) != hipSuccess ||
       (e = dev_alloc(&p->flags, 1)) != hipSuccess ||
       (e = dev_alloc(&p->ll_ws, 2 * W)) != hipSuccess ||
       (fit_ws > 0 && (e = dev_alloc(&p->fit_ws, (size_t)(p->fit_ws_floats = fit_ws))) !=

@@ -40,6 +40,7 @@ struct Events {
   const float* end_gap;  // [W] T - t_last (T for an empty window), FP64-computed
   const int32_t* order;  // [W] window ids, largest first
   const int32_t* counts; // [W][M] events per dimension (lane-major plans only, else null)
+  int64_t n_big;         // lane-major plans: windows of >= kBigWindow events (a prefix of order)
 };
 
 // Fit options as the kernels read them.
@@ -64,6 +65,7 @@ hipError_t choose_init(const double* ll_warm, const double* ll_cold, int64_t W, 
                        const float* mu_c, const float* al_c, const float* be_c, float* mu,
                        float* alpha, float* beta, int32_t* used_warm, hipStream_t s);
 
+// Zeroes the two queue heads counter[0..1].
 inline void reset_counter(int* counter, hipStream_t s) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
 }
@@ -73,6 +75,10 @@ inline void reset_counter(int* counter, hipStream_t s) {
 #endif
 // Largest M whose shared-decay plans use the lane-major layout and kernels.
 constexpr int kLaneMajorMaxM = MDHP_LANE_MAJOR_MAX_M;
+// Lane-major windows of at least this many events are laid out for, and
+// run by, a whole workgroup (256 chunks); shorter ones by one wavefront (64).
+constexpr int64_t kBigWindow = 4096;
+__host__ __device__ inline int64_t lane_team(int64_t n) { return n >= kBigWindow ? kBlock : 64; }
 
 // Lane-major (one chunk per lane, one window per wave) kernels, M <= 16.
 hipError_t lpc_eval(const Events& ev, int M, const float* mu, const float* alpha,
@@ -81,7 +87,7 @@ hipError_t lpc_eval(const Events& ev, int M, const float* mu, const float* alpha
 hipError_t lpc_fit(const Events& ev, int M, const FitParams& o, float* mu, float* alpha,
                    float* beta, double* ll, int* steps, int* status, int* evals, float* ws,
                    int64_t ws_floats, int* counter, hipStream_t s);
-int64_t lpc_lbfgs_workspace(int M, int64_t W);
+int64_t lpc_lbfgs_workspace(int M, int64_t W, int64_t n_big);
 
 // Workgroup-per-window kernels for the compact layout, 16 < M <= 64.
 hipError_t shared_eval(const Events& ev, int M, const float* mu, const float* alpha,

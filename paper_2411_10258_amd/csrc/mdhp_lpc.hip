@@ -1,36 +1,44 @@
 // Shared-decay likelihood, gradient and persistent fits for M <= 16 with one
 // chunk of events per lane ("lane per chunk").
 //
-// Each wavefront owns one window at a time.  The window's N events are cut
-// into 64 contiguous chunks of c = ceil(N / 64) events, one per lane, and the
-// plan stores them lane-major: event j of lane l's chunk sits at slot
-// begin + 64 j + l (padding slots: gap 0, dimension 0xFF), so every step of
-// the 64 lanes reads 64 consecutive gaps and dimension bytes.
+// A team of NW wavefronts owns one window at a time: one wavefront for
+// ordinary windows, the whole 4-wave workgroup for windows of at least
+// kBigWindow events.  Those come first in the largest-first order, so a
+// persistent workgroup takes big windows as a team, then its waves take the
+// rest one each.  The window's N events are cut into T = 64 NW contiguous
+// chunks of c = ceil(N / T) events, one per lane of the team, and the plan
+// stores them lane-major: event j of chunk t sits at slot begin + T j + t
+// (padding slots: gap 0, dimension 0xFF), so every step of a wave reads 64
+// consecutive gaps and dimension bytes.
 //
 // Every lane keeps the whole decay state of its chunk in registers: R_n, S_n
 // and the pending counts P_n for n < MP (MP = M rounded up to 4, 8 or 16),
 //   R_n(i) = sum_{k: d_k = n, t_k < t_i} e^{-beta (t_i - t_k)}      (Part1's inner sum, Eq. (5))
 //   S_n(i) = sum_{k: d_k = n, t_k < t_i} (t_i - t_k) e^{-beta (t_i - t_k)}   (= -dR/dbeta)
-// and applies the exponential-kernel recursion R <- a (R + P), S <- a S + dt R,
-// a = e^{-beta dt}, where P holds the events at the previous time (folded in
-// only when time moves on, so equal times never excite each other).  No
-// lane waits for another.  The chunk carries (zero-start end state, product
-// of decays A, summed gaps delta, "has a positive gap" flag) are combined
-// across lanes by an inclusive scan (DPP row shifts, then row broadcasts);
-// its exclusive form gives every lane the exact start state of its chunk,
-// and a second pass over the chunk evaluates
+// and applies the exponential-kernel recursion to the inclusive state
+// Rin = R + P (events at or before the current time):
+//   Rin <- a Rin + e_d,  S <- a (S + dt Rin),  R = a Rin if dt > 0 (else R stays),
+// a = e^{-beta dt}, exactly 1 at equal times, which therefore never excite
+// each other.  No lane waits for another.  The chunk carries (zero-start end
+// state, product of decays A, summed gaps delta, "has a positive gap" flag)
+// are combined across the team by an inclusive scan (DPP row shifts and row
+// broadcasts inside a wave, then the waves' totals in order); its exclusive
+// form gives every lane the exact start state of its chunk, and a second
+// pass over the chunk evaluates
 //   lambda_i = mu_m + sum_n alpha_mn R_n(i),   m = d_i           (Eq. (2) at t_i)
 //   ll += log lambda_i,  G_R[m][n] += R_n(i) / lambda_i,  Gmu[m] += 1 / lambda_i,
 //   Gb += sum_n alpha_mn S_n(i) / lambda_i.
 // G_R is a sum of one outer product per event, e_{d_i} (R(i) / lambda_i)^T;
-// over a step of 64 events that is a 16 x 64 by 64 x M matrix product, run on
-// the matrix cores (v_mfma_f32_16x16x4_f32) from a column-major LDS staging of
-// the step (LDS float atomics, one per event and component, are ~6x slower
-// than the whole rest of the pass on gfx950).  Gmu and Gb are per-lane sums;
-// the per-dimension counts N_m come with the plan.  The compensator (Part2 +
-// Part3, Appendix B) comes from the window's end state advanced to T:
+// over a step of a wave's 64 events that is a 16 x 64 by 64 x M matrix
+// product, run on the matrix cores (v_mfma_f32_16x16x4_f32) from a
+// column-major LDS staging of the step (LDS float atomics, one per event and
+// component, are ~6x slower than the whole rest of the pass on gfx950).
+// Gmu and Gb are per-lane sums; the per-dimension counts N_m come with the
+// plan.  The compensator (Part2 + Part3, Appendix B) comes from the window's
+// end state advanced to T:
 //   E_n = sum_{k: d_k = n} e^{-beta (T - t_k)},  F_n = sum (T - t_k) e^{-beta (T - t_k)}.
-// The fits run per wave with wave-level reductions: no workgroup barriers.
+// Everything that leaves a lane is reduced in FP64 in a fixed order, so a
+// window's results do not depend on the rest of the batch or on timing.
 
 #include "mdhp_device.h"
 
@@ -40,25 +48,11 @@ namespace {
 
 constexpr int kWaves = kBlock / 64;  // wavefronts per workgroup
 constexpr int kPad = 0xFF;           // dimension byte of a padding slot
-constexpr int kSpan = 16;            // steps (64 events each) per FP32 accumulation span
+constexpr int kSpan = 16;            // steps per FP32 span of the MFMA sums
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <int MP>
-struct alignas(16) LpcWave {
-  static constexpr int Q = MP + 1;  // row stride of gR64: G_R[m][0..MP-1], Gmu[m]
-  float alpha[MP * MP];             // [m * MP + n], zero outside M x M
-  float mu[MP];                     // zero outside M
-  float colsum[MP];                 // sum_m alpha_mn
-  float vst[MP * 64];               // step staging, column-major: w_k R_n(k) at [n * 64 + k]
-  float hot[16 * 64];               // one-hot of the step's targets: 1 at [d_k * 64 + k], else 0
-  float gmu[64 * Q];                // per-lane sums of w over the lane's events of target m: [lane * Q + m]
-  double gR64[MP * Q];              // window sums (FP64 over spans): G_R, Gmu in column MP
-  double En[MP], Fn[MP];            // E_n, F_n
-  double Cn[MP];                    // (N_n - E_n) / beta
-  double scal[2];                   // ll, d ll / d beta
-  float beta;
-};
+// ---------------------------------------------------------------- wave level
 
 template <class F>
 __device__ __forceinline__ F wave_sum(F v) {
@@ -71,6 +65,19 @@ __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int k = 32; k > 0; k >>= 1) v = fmax(v, __shfl_xor(v, k, 64));
   return v;
+}
+
+// A value every lane of the wave holds, moved to a scalar register (the
+// compiler then treats it, and what is derived from it, as uniform).
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uni(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ double uni(double x) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
 // Orders the wave's earlier LDS accesses before its later ones, across lanes.
@@ -94,8 +101,8 @@ __device__ __forceinline__ float bcast31(float v) {
                                                                 0x143, 0xC, 0xF, false));
 }
 
-// Chunk carry of one lane: the state a zero start reaches at the end of the
-// chunk, the product of its decays A, the sum of its gaps D, and F = 1 if a
+// Chunk carry: the state a zero start reaches at the end of a run of
+// events, the product of its decays A, the sum of its gaps D, and F = 1 if a
 // gap is positive (then the pending counts of the start are folded in).
 template <int MP>
 struct Carry {
@@ -103,8 +110,8 @@ struct Carry {
   float A, D, F;
 };
 
-// One scan step: where `take`, the carry becomes (segment read through
-// SHIFT) followed by the lane's own segment.
+// One step of the in-wave scan: where `take`, the lane's run b becomes the
+// run ending at the lane chosen by SHIFT (a DPP lane map) followed by b.
 template <int MP, class SHIFT>
 __device__ __forceinline__ void scan_step(Carry<MP>& b, bool take, SHIFT shift) {
   const float aA = shift(b.A), aD = shift(b.D), aF = shift(b.F);
@@ -125,7 +132,7 @@ __device__ __forceinline__ void scan_step(Carry<MP>& b, bool take, SHIFT shift) 
   b.F = take ? fmaxf(b.F, aF) : b.F;
 }
 
-// Inclusive scan of the lanes' carries in lane order.
+// Inclusive scan of the wave's carries in lane order.
 template <int MP>
 __device__ __forceinline__ void scan_carries(Carry<MP>& c, int lane) {
   const int lr = lane & 15;
@@ -137,63 +144,144 @@ __device__ __forceinline__ void scan_carries(Carry<MP>& c, int lane) {
   scan_step<MP>(c, lane >= 32, [](float v) { return bcast31(v); });
 }
 
-// G_R over one step: the 64 events' rows w_k R(k) (staged column-major in
-// vst) summed by target, G_R[m][n] += sum_k [d_k = m] w_k R_n(k), as the
-// product H^T V of the step's one-hot targets H (64 x 16) and V (64 x MP):
-// sixteen v_mfma_f32_16x16x4_f32 with K running over the events.  Lane l
-// supplies A = H[16q + s][l % 16] and B = V[16q + s][l % 16] (q = l / 16) for
-// instruction s, and holds G_R[4q + r][l % 16] in acc[r].
+// ---------------------------------------------------------------- team level
+
+// LDS of one team (NW wavefronts sharing a window).
+template <int MP, int NW>
+struct alignas(16) Team {
+  static constexpr int Q = MP + 1;   // row stride of gR64: G_R[m][0..MP-1], Gmu[m]
+  static constexpr int T = 64 * NW;  // lanes (= chunks) of the team
+  static constexpr int XC = 3 * MP + 4;
+  float alpha[MP * MP];              // [m * MP + n], zero outside M x M
+  float mu[MP];                      // zero outside M
+  float colsum[MP];                  // sum_m alpha_mn
+  float vst[NW][MP * 64];            // per wave: step staging, w_k R_n(k) at [n * 64 + k]
+  float hot[NW][16 * 64];            // per wave: 1 at [d_k * 64 + k] during a step, else 0
+  float gmu[NW][64 * Q];             // per lane: sum of w over its events of target m
+  double gpart[NW][MP * MP + MP];    // per wave: FP64 G_R (MFMA spans) and Gmu partials
+  float xc[NW][XC];                  // per wave: its inclusive total (R, S, P, A, D, F), then
+                                     // the carry of the team's earlier waves
+  double gR64[MP * Q];               // window sums: G_R, Gmu in column MP
+  double En[MP], Fn[MP];             // E_n, F_n
+  double Cn[MP];                     // (N_n - E_n) / beta
+  double scal[2];                    // ll, d ll / d beta
+  double red[NW][2];                 // cross-wave reduction slots
+  double rho[kMaxHistory], alf[kMaxHistory];  // L-BFGS two-loop scalars
+  int q;                             // queue position broadcast to the team
+  float beta;
+};
+
+template <int NW>
+__device__ __forceinline__ int team_tid() {
+  return threadIdx.x & (64 * NW - 1);
+}
+
+template <int NW>
+__device__ __forceinline__ void team_sync() {
+  if constexpr (NW == 1) wave_sync();
+  else __syncthreads();
+}
+
+// Sums of x and y over the team (every lane gets them; fixed order).
+template <int MP, int NW>
+__device__ __forceinline__ void team_sum2(Team<MP, NW>& sh, double& x, double& y) {
+  x = wave_sum(x);
+  y = wave_sum(y);
+  if constexpr (NW > 1) {
+    const int t = team_tid<NW>();
+    __syncthreads();
+    if ((t & 63) == 0) {
+      sh.red[t >> 6][0] = x;
+      sh.red[t >> 6][1] = y;
+    }
+    __syncthreads();
+    x = y = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      x += sh.red[k][0];
+      y += sh.red[k][1];
+    }
+  }
+  x = uni(x);
+  y = uni(y);
+}
+
+template <int MP, int NW>
+__device__ __forceinline__ double team_sum(Team<MP, NW>& sh, double x) {
+  double y = 0.0;
+  team_sum2(sh, x, y);
+  return x;
+}
+
+template <int MP, int NW>
+__device__ __forceinline__ double team_max(Team<MP, NW>& sh, double x) {
+  x = wave_max(x);
+  if constexpr (NW > 1) {
+    const int t = team_tid<NW>();
+    __syncthreads();
+    if ((t & 63) == 0) sh.red[t >> 6][0] = x;
+    __syncthreads();
+    x = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) x = fmax(x, sh.red[k][0]);
+  }
+  return uni(x);
+}
+
+// True on every lane if `bad` is true on any lane of the team.
+template <int MP, int NW>
+__device__ __forceinline__ bool team_any(Team<MP, NW>& sh, bool bad) {
+  return team_max(sh, __any(bad) ? 1.0 : 0.0) != 0.0;
+}
+
+// G_R over one step of a wave: the 64 events' rows w_k R(k) (staged
+// column-major in vst) summed by target, G_R[m][n] += sum_k [d_k = m] w_k R_n(k),
+// as the product H^T V of the step's one-hot targets H (64 x 16) and V
+// (64 x MP): sixteen v_mfma_f32_16x16x4_f32 with K running over the events,
+// in two independent accumulator chains.  Lane l supplies A = H[16q + s][l % 16]
+// and B = V[16q + s][l % 16] (q = l / 16) to instruction s, and holds
+// G_R[4q + r][l % 16] in acc0[r] + acc1[r].
 template <int MP>
-__device__ __forceinline__ void step_outer(const LpcWave<MP>& sh, f32x4& acc) {
+__device__ __forceinline__ void step_outer(const float* vst, const float* hot, f32x4& acc0,
+                                           f32x4& acc1) {
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, base = (lane >> 4) * 16;
   f32x4 a[4], b[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    a[i] = *reinterpret_cast<const f32x4*>(&sh.hot[col * 64 + base + 4 * i]);
-    b[i] = col < MP ? *reinterpret_cast<const f32x4*>(&sh.vst[(col % MP) * 64 + base + 4 * i])
+    a[i] = *reinterpret_cast<const f32x4*>(&hot[col * 64 + base + 4 * i]);
+    b[i] = col < MP ? *reinterpret_cast<const f32x4*>(&vst[(col % MP) * 64 + base + 4 * i])
                     : f32x4{0.f, 0.f, 0.f, 0.f};
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][e], b[i][e], acc, 0, 0, 0);
-}
-
-// Adds the FP32 span sums of G_R (MFMA accumulators) into the FP64 window
-// sums and clears them.
-template <int MP>
-__device__ __forceinline__ void flush_span(LpcWave<MP>& sh, f32x4& acc) {
-  const int lane = threadIdx.x & 63;
-  const int col = lane & 15, row0 = (lane >> 4) * 4;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    if (row0 + r < MP && col < MP) sh.gR64[(row0 + r) * LpcWave<MP>::Q + col] += (double)acc[r];
-    acc[r] = 0.f;
+  for (int i = 0; i < 4; ++i) {
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][0], b[i][0], acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][1], b[i][1], acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][2], b[i][2], acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][3], b[i][3], acc1, 0, 0, 0);
   }
 }
 
-// Evaluates the wave's window with the parameters in its LDS slot (alpha,
-// mu, colsum, beta; sums cleared; counts = the window's N_m).  On return
-// (all lanes): scal[0] = ll; with GRAD also gR64 (G_R and, in column MP,
-// Gmu), Cn, Fn and scal[1] = d ll / d beta.
-// Per-lane and LDS sums run in FP32 over spans of kSpan steps and are
-// accumulated in FP64 across spans.
-template <int MP, bool GRAD>
-__device__ __forceinline__ void lpc_eval(LpcWave<MP>& sh, const float* __restrict__ dtg,
-                                         const uint8_t* __restrict__ dg, int64_t begin, int n,
-                                         double T, float end_gap, const int32_t* counts, int M) {
-  constexpr int Q = LpcWave<MP>::Q;
-  const int lane = threadIdx.x & 63;
-  const float beta = sh.beta;
-  const int c = (n + 63) / 64;
-  const float* __restrict__ dtw = dtg + begin + lane;
-  const uint8_t* __restrict__ dw = dg + begin + lane;
+// Evaluates the team's window with the parameters in its LDS (alpha, mu,
+// colsum, beta; gmu cleared; counts = the window's N_m).  On return (all
+// lanes, after a team sync): scal[0] = ll; with GRAD also gR64 (G_R and, in
+// column MP, Gmu), Cn, Fn and scal[1] = d ll / d beta.  FP32 sums run over
+// spans of kSpan steps (MFMA) or over the lane's chunk, then FP64.
+template <int MP, int NW, bool GRAD>
+__device__ __forceinline__ void team_eval(Team<MP, NW>& sh, const float* __restrict__ dtg,
+                                          const uint8_t* __restrict__ dg, int64_t begin, int n,
+                                          double Tw, float end_gap,
+                                          const int32_t* __restrict__ counts, int M) {
+  constexpr int Q = Team<MP, NW>::Q;
+  constexpr int T = Team<MP, NW>::T;
+  const int t = team_tid<NW>();
+  const int lane = t & 63, wv = t >> 6;
+  const float beta = uni(sh.beta);
+  const int c = (n + T - 1) / T;
+  const float* __restrict__ dtw = dtg + begin + t;
+  const uint8_t* __restrict__ dw = dg + begin + t;
 
-  // Pass 1: the chunk's carry from a zero start.  The lane runs the
-  // inclusive state Rin = R + P (events at or before the current time):
-  //   Rin <- a Rin + e_d,   S <- a (S + dt Rin),
-  // which needs no case for equal times because a = 1 exactly when dt = 0.
+  // Pass 1: the chunk's carry from a zero start.
   Carry<MP> cr;
   float Rin[MP];
 #pragma unroll
@@ -207,8 +295,8 @@ __device__ __forceinline__ void lpc_eval(LpcWave<MP>& sh, const float* __restric
       const float dt = dt_n;
       const int d = d_n;
       if (j + 1 < c) {
-        dt_n = dtw[(int64_t)(j + 1) * 64];
-        d_n = dw[(int64_t)(j + 1) * 64];
+        dt_n = dtw[(int64_t)(j + 1) * T];
+        d_n = dw[(int64_t)(j + 1) * T];
       }
       const float a = dt > 0.f ? __expf(-beta * dt) : 1.f;
 #pragma unroll
@@ -225,20 +313,94 @@ __device__ __forceinline__ void lpc_eval(LpcWave<MP>& sh, const float* __restric
   {
 #pragma unroll
     for (int m = 0; m < MP; ++m) cr.P[m] = 0.f;
-    const int len = min(max(n - lane * c, 0), c);
+    const int len = (int)min<int64_t>(max<int64_t>((int64_t)n - (int64_t)t * c, 0), c);
     for (int j = len - 1; j >= 0; --j) {
-      const int d = dw[(int64_t)j * 64];
+      const int d = dw[(int64_t)j * T];
 #pragma unroll
       for (int m = 0; m < MP; ++m) cr.P[m] += m == d ? 1.f : 0.f;
-      if (dtw[(int64_t)j * 64] > 0.f) break;
+      if (dtw[(int64_t)j * T] > 0.f) break;
     }
 #pragma unroll
     for (int m = 0; m < MP; ++m) cr.R[m] = Rin[m] - cr.P[m];
   }
   cr.F = cr.D > 0.f ? 1.f : 0.f;
   scan_carries<MP>(cr, lane);
-  // Lane 63 now holds the window's end state: E_n and F_n at T.
-  if (lane == 63) {
+  // Cross-wave: xc[w] first receives wave w's total, then (lanes m <= MP of
+  // wave 0, one component each, in wave order) the carry X of waves 0..w-1;
+  // every lane's inclusive carry becomes X followed by its in-wave prefix.
+  if constexpr (NW > 1) {
+    if (lane == 63) {
+#pragma unroll
+      for (int m = 0; m < MP; ++m) {
+        sh.xc[wv][m] = cr.R[m];
+        sh.xc[wv][MP + m] = cr.S[m];
+        sh.xc[wv][2 * MP + m] = cr.P[m];
+      }
+      sh.xc[wv][3 * MP] = cr.A;
+      sh.xc[wv][3 * MP + 1] = cr.D;
+      sh.xc[wv][3 * MP + 2] = cr.F;
+    }
+    __syncthreads();
+    if (wv == 0) {
+      // Lane m < MP: component m; lane MP: the shared A, D, F.
+      const int m = lane < MP ? lane : 0;
+      float xr = 0.f, xs = 0.f, xp = 0.f, xa = 1.f, xd = 0.f, xf = 0.f;
+      float out[NW][3];
+#pragma unroll
+      for (int k = 0; k + 1 < NW; ++k) {
+        const float br = sh.xc[k][m], bs = sh.xc[k][MP + m], bp = sh.xc[k][2 * MP + m];
+        const float ba = sh.xc[k][3 * MP], bd = sh.xc[k][3 * MP + 1], bf = sh.xc[k][3 * MP + 2];
+        const float Xs = xr + xp;
+        const bool f = bf != 0.f;
+        const float nr = f ? fmaf(ba, Xs, br) : xr;
+        const float ns = f ? fmaf(ba, fmaf(bd, Xs, xs), bs) : xs;
+        const float np = f ? bp : xp + bp;
+        xr = nr;
+        xs = ns;
+        xp = np;
+        xa *= ba;
+        xd += bd;
+        xf = fmaxf(xf, bf);
+        out[k + 1][0] = lane < MP ? xr : xa;
+        out[k + 1][1] = lane < MP ? xs : xd;
+        out[k + 1][2] = lane < MP ? xp : xf;
+      }
+      wave_sync();  // every lane of wave 0 has read the totals
+#pragma unroll
+      for (int k = 1; k < NW; ++k) {
+        if (lane < MP) {
+          sh.xc[k][m] = out[k][0];
+          sh.xc[k][MP + m] = out[k][1];
+          sh.xc[k][2 * MP + m] = out[k][2];
+        } else if (lane == MP) {
+          sh.xc[k][3 * MP] = out[k][0];
+          sh.xc[k][3 * MP + 1] = out[k][1];
+          sh.xc[k][3 * MP + 2] = out[k][2];
+        }
+      }
+    }
+    __syncthreads();
+    if (wv > 0) {  // cr <- X followed by cr
+      const float* x = sh.xc[wv];
+      const bool f = cr.F != 0.f;
+#pragma unroll
+      for (int m = 0; m < MP; ++m) {
+        const float aR = x[m], aS = x[MP + m], aP = x[2 * MP + m];
+        const float Xs = aR + aP;
+        const float r = f ? fmaf(cr.A, Xs, cr.R[m]) : aR;
+        const float sv = f ? fmaf(cr.A, fmaf(cr.D, Xs, aS), cr.S[m]) : aS;
+        const float p = f ? cr.P[m] : aP + cr.P[m];
+        cr.R[m] = r;
+        cr.S[m] = sv;
+        cr.P[m] = p;
+      }
+      cr.A *= x[3 * MP];
+      cr.D += x[3 * MP + 1];
+      cr.F = fmaxf(cr.F, x[3 * MP + 2]);
+    }
+  }
+  // The team's last lane now holds the window's end state: E_n, F_n at T.
+  if (t == T - 1) {
     const double gap = (double)end_gap;
     const double ea = exp(-(double)beta * gap);
 #pragma unroll
@@ -248,22 +410,34 @@ __device__ __forceinline__ void lpc_eval(LpcWave<MP>& sh, const float* __restric
       sh.Fn[m] = ea * (double)cr.S[m] + gap * E;
     }
   }
-  // Exclusive form: lane l starts from the state after chunks 0 .. l-1
-  // (strict R, inclusive Rin = R + P, S).
+  // Exclusive form: lane t starts from the state after chunks 0 .. t-1
+  // (strict R, inclusive Rin = R + P, S); lane 0 of a later wave from the
+  // carry of the earlier waves.
   float R[MP], S[MP];
+  const bool from_x = NW > 1 && lane == 0 && wv > 0;
+  const float* xw = sh.xc[wv];
 #pragma unroll
   for (int m = 0; m < MP; ++m) {
-    const float pR = __shfl_up(cr.R[m], 1, 64), pS = __shfl_up(cr.S[m], 1, 64);
-    const float pP = __shfl_up(cr.P[m], 1, 64);
-    R[m] = lane == 0 ? 0.f : pR;
-    S[m] = lane == 0 ? 0.f : pS;
-    Rin[m] = lane == 0 ? 0.f : pR + pP;
+    float pR = __shfl_up(cr.R[m], 1, 64), pS = __shfl_up(cr.S[m], 1, 64);
+    float pP = __shfl_up(cr.P[m], 1, 64);
+    if (lane == 0) {
+      pR = from_x ? xw[m] : 0.f;
+      pS = from_x ? xw[MP + m] : 0.f;
+      pP = from_x ? xw[2 * MP + m] : 0.f;
+    }
+    R[m] = pR;
+    S[m] = pS;
+    Rin[m] = pR + pP;
   }
-  // Pass 2: intensities, log-likelihood and gradient sums.  At an event
-  // with dt > 0 the strict state is R = a Rin; at an equal time it stays.
+  // Pass 2: intensities, log-likelihood and gradient sums.
   float llp = 0.f, gbp = 0.f;
   double ll64 = 0.0, gb64 = 0.0;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  double* gpart = sh.gpart[wv];
+  const int gcol = lane & 15, grow0 = (lane >> 4) * 4;  // this lane's G_R[grow0 + r][gcol]
+  float* vst = sh.vst[wv];
+  float* hot = sh.hot[wv];
+  float* gmu = &sh.gmu[wv][lane * Q];
   {
     float dt_n = c > 0 ? dtw[0] : 0.f;
     int d_n = c > 0 ? (int)dw[0] : kPad;
@@ -271,8 +445,8 @@ __device__ __forceinline__ void lpc_eval(LpcWave<MP>& sh, const float* __restric
       const float dt = dt_n;
       const int dr = d_n;
       if (j + 1 < c) {
-        dt_n = dtw[(int64_t)(j + 1) * 64];
-        d_n = dw[(int64_t)(j + 1) * 64];
+        dt_n = dtw[(int64_t)(j + 1) * T];
+        d_n = dw[(int64_t)(j + 1) * T];
       }
       const bool v = dr != kPad;
       const int d = v ? dr : 0;
@@ -280,124 +454,211 @@ __device__ __forceinline__ void lpc_eval(LpcWave<MP>& sh, const float* __restric
       const float a = f ? __expf(-beta * dt) : 1.f;
       const float* arow = &sh.alpha[d * MP];
       float lam = sh.mu[d], asum = 0.f;
+      float g_old = 0.f;
+      if constexpr (GRAD) g_old = gmu[d];
 #pragma unroll
       for (int m = 0; m < MP; ++m) {
-        const float t = a * Rin[m];
+        const float tm = a * Rin[m];
         S[m] = a * fmaf(dt, Rin[m], S[m]);
-        R[m] = f ? t : R[m];
-        Rin[m] = t + (m == dr ? 1.f : 0.f);
+        R[m] = f ? tm : R[m];
+        Rin[m] = tm + (m == dr ? 1.f : 0.f);
         const float al = arow[m];
         lam = fmaf(al, R[m], lam);
         asum = fmaf(al, S[m], asum);
       }
       if (v) llp += __logf(lam);
       if constexpr (GRAD) {
-        // Padding events stage w = 0 (their one-hot row is 0, target 0).
+        // Padding events stage w = 0 (target 0, so their one-hot entry adds 0).
         const float w = v ? __builtin_amdgcn_rcpf(lam) : 0.f;
         gbp = fmaf(w, asum, gbp);
-        sh.gmu[lane * Q + d] += w;  // the lane's own row: no other lane writes it
+        gmu[d] = g_old + w;  // the lane's own row: no other lane touches it
 #pragma unroll
-        for (int m = 0; m < MP; ++m) sh.vst[m * 64 + lane] = w * R[m];
-        sh.hot[d * 64 + lane] = 1.f;
+        for (int m = 0; m < MP; ++m) vst[m * 64 + lane] = w * R[m];
+        hot[d * 64 + lane] = 1.f;
         wave_sync();
-        step_outer(sh, acc);
+        step_outer<MP>(vst, hot, acc0, acc1);
         wave_sync();
-        sh.hot[d * 64 + lane] = 0.f;
+        hot[d * 64 + lane] = 0.f;
+        if (j % kSpan == kSpan - 1 || j + 1 == c) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)  // the lane's own entries: no other lane touches them
+            if (grow0 + r < MP && gcol < MP)
+              gpart[(grow0 + r) * MP + gcol] += (double)acc0[r] + (double)acc1[r];
+          acc0 = f32x4{0.f, 0.f, 0.f, 0.f};
+          acc1 = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
       }
       if (j % kSpan == kSpan - 1 || j + 1 == c) {
         ll64 += (double)llp;
         gb64 += (double)gbp;
         llp = gbp = 0.f;
-        if constexpr (GRAD) flush_span(sh, acc);
       }
     }
   }
-  wave_sync();
-  if constexpr (GRAD) {  // Gmu[m]: the lanes' sums, in FP64
+  if constexpr (GRAD) {
+    // Each wave's Gmu partials (FP64) next to its G_R partials, then the
+    // team's sums over waves in order.
+    wave_sync();
     if (lane < MP) {
+      const float* gw = sh.gmu[wv];
       double g[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 16
-      for (int l = 0; l < 64; ++l) g[l & 3] += (double)sh.gmu[l * Q + lane];
-      sh.gR64[lane * Q + MP] = (g[0] + g[1]) + (g[2] + g[3]);
+      for (int l = 0; l < 64; ++l) g[l & 3] += (double)gw[l * Q + lane];
+      gpart[MP * MP + lane] = (g[0] + g[1]) + (g[2] + g[3]);
     }
-    wave_sync();
+    team_sync<NW>();
+    for (int e = t; e < MP * Q; e += T) {
+      const int m = e / Q, k = e % Q;
+      const int src = k < MP ? m * MP + k : MP * MP + m;
+      double s = 0.0;
+#pragma unroll
+      for (int wk = 0; wk < NW; ++wk) s += sh.gpart[wk][src];
+      sh.gR64[e] = s;
+    }
   }
-  // Compensator: lane m < M finishes source dimension m; one FP64 wave sum
-  // each for ll and d ll / d beta.
+  team_sync<NW>();
+  // Compensator: lane m < M finishes source dimension m.
   const double b = (double)beta;
   double x = ll64, y = gb64;
-  if (lane < M) {
-    const double C = ((double)counts[lane] - sh.En[lane]) / b;
-    const double cs = (double)sh.colsum[lane];
-    x -= T * (double)sh.mu[lane] + cs * C;
-    y += cs * (sh.Fn[lane] - C) / b;
-    sh.Cn[lane] = C;
-  } else if (lane < MP) {
-    sh.Cn[lane] = 0.0;
+  if (t < M) {
+    const double C = ((double)counts[t] - sh.En[t]) / b;
+    const double cs = (double)sh.colsum[t];
+    x -= Tw * (double)sh.mu[t] + cs * C;
+    y += cs * (sh.Fn[t] - C) / b;
+    sh.Cn[t] = C;
+  } else if (t < MP) {
+    sh.Cn[t] = 0.0;
   }
-  x = wave_sum(x);
-  y = wave_sum(y);
-  if (lane == 0) {
+  team_sum2(sh, x, y);
+  if (t == 0) {
     sh.scal[0] = x;
     sh.scal[1] = -y;
   }
-  wave_sync();
+  team_sync<NW>();
 }
 
-template <int MP>
-__device__ __forceinline__ void lpc_colsum(LpcWave<MP>& sh, int M) {
-  const int lane = threadIdx.x & 63;
-  wave_sync();
-  if (lane < MP) {
+template <int MP, int NW>
+__device__ __forceinline__ void team_colsum(Team<MP, NW>& sh, int M) {
+  const int t = team_tid<NW>();
+  team_sync<NW>();
+  if (t < MP) {
     float s = 0.f;
-    for (int m = 0; m < M; ++m) s += sh.alpha[m * MP + lane];
-    sh.colsum[lane] = s;
+    for (int m = 0; m < M; ++m) s += sh.alpha[m * MP + t];
+    sh.colsum[t] = s;
   }
-  wave_sync();
+  team_sync<NW>();
 }
 
-template <int MP>
-__device__ __forceinline__ void lpc_load(LpcWave<MP>& sh, const float* __restrict__ mu,
-                                         const float* __restrict__ alpha,
-                                         const float* __restrict__ beta, int64_t w, int M) {
-  const int lane = threadIdx.x & 63;
-  wave_sync();
-  for (int e = lane; e < MP * MP; e += 64) {
+template <int MP, int NW>
+__device__ __forceinline__ void team_load(Team<MP, NW>& sh, const float* __restrict__ mu,
+                                          const float* __restrict__ alpha,
+                                          const float* __restrict__ beta, int64_t w, int M) {
+  const int t = team_tid<NW>();
+  team_sync<NW>();
+  for (int e = t; e < MP * MP; e += Team<MP, NW>::T) {
     const int m = e / MP, n = e % MP;
     sh.alpha[e] = (m < M && n < M) ? alpha[(w * M + m) * M + n] : 0.f;
   }
-  if (lane < MP) sh.mu[lane] = lane < M ? mu[w * M + lane] : 0.f;
-  if (lane == 0) sh.beta = beta[w];
-  lpc_colsum(sh, M);
+  if (t < MP) sh.mu[t] = t < M ? mu[w * M + t] : 0.f;
+  if (t == 0) sh.beta = beta[w];
+  team_colsum(sh, M);
 }
 
-// Clears the gradient sums of the wave's slot.
-template <int MP>
-__device__ __forceinline__ void lpc_zero(LpcWave<MP>& sh) {
-  const int lane = threadIdx.x & 63;
-  wave_sync();
-  for (int e = lane; e < 64 * LpcWave<MP>::Q; e += 64) sh.gmu[e] = 0.f;
-  for (int e = lane; e < MP * LpcWave<MP>::Q; e += 64) sh.gR64[e] = 0.0;
-  wave_sync();
+// Clears the Gmu and G_R partial sums (before every evaluation with gradient).
+template <int MP, int NW>
+__device__ __forceinline__ void team_zero(Team<MP, NW>& sh) {
+  const int t = team_tid<NW>();
+  team_sync<NW>();
+  float* g = &sh.gmu[0][0];
+  for (int e = t; e < NW * 64 * Team<MP, NW>::Q; e += Team<MP, NW>::T) g[e] = 0.f;
+  double* gp = &sh.gpart[0][0];
+  for (int e = t; e < NW * (MP * MP + MP); e += Team<MP, NW>::T) gp[e] = 0.0;
+  team_sync<NW>();
 }
 
-// Clears the wave's one-hot staging (kept zero between steps).
-template <int MP>
-__device__ __forceinline__ void lpc_init(LpcWave<MP>& sh) {
-  const int lane = threadIdx.x & 63;
-  for (int e = lane; e < 16 * 64; e += 64) sh.hot[e] = 0.f;
-  wave_sync();
+// Clears the one-hot staging (kept zero between steps).
+template <int MP, int NW>
+__device__ __forceinline__ void team_init(Team<MP, NW>& sh) {
+  const int t = team_tid<NW>();
+  float* h = &sh.hot[0][0];
+  for (int e = t; e < NW * 16 * 64; e += Team<MP, NW>::T) h[e] = 0.f;
+  team_sync<NW>();
 }
 
-// Next queue position of the wave: the first is fixed by the wave's place
-// in the grid, the rest come from the atomic queue head.
-__device__ __forceinline__ int lpc_next(int* counter, bool first) {
-  const int lane = threadIdx.x & 63;
+// Next window of the team: queue position `first_q` the first time, then
+// from the atomic head `head` (offset by the positions handed out at start).
+template <int MP, int NW>
+__device__ __forceinline__ int team_next(Team<MP, NW>& sh, int* head, bool first, int first_q,
+                                         int started) {
+  const int t = team_tid<NW>();
   int q = 0;
-  if (lane == 0)
-    q = first ? (int)(blockIdx.x * kWaves + (threadIdx.x >> 6))
-              : atomicAdd(counter, 1) + (int)(gridDim.x * kWaves);
-  return __shfl(q, 0, 64);
+  if (t == 0) q = first ? first_q : atomicAdd(head, 1) + started;
+  if constexpr (NW == 1) {
+    return uni(q);  // lane 0 of the wave holds it
+  } else {
+    __syncthreads();
+    if (t == 0) sh.q = q;
+    __syncthreads();
+    return uni(sh.q);
+  }
+}
+
+// Both team shapes share the workgroup's LDS.
+template <int MP>
+union BlockLds {
+  Team<MP, kWaves> big;
+  Team<MP, 1> small[kWaves];
+};
+
+// Runs body(team LDS, window) over the big windows (team = workgroup), then
+// over the rest (team = wavefront).  counter[0] and counter[1] are the heads
+// of the two queues.
+template <int MP, class BIG, class SMALL>
+__device__ __forceinline__ void for_windows(BlockLds<MP>& lds, const Events& ev, int* counter,
+                                            BIG&& big_body, SMALL&& small_body) {
+  const int nb = (int)ev.n_big;
+  {
+    Team<MP, kWaves>& sh = lds.big;
+    team_init(sh);
+    for (int q = team_next(sh, &counter[0], true, (int)blockIdx.x, (int)gridDim.x); q < nb;
+         q = team_next(sh, &counter[0], false, 0, (int)gridDim.x))
+      big_body(sh, (int64_t)ev.order[q]);
+    __syncthreads();
+  }
+  {
+    const int wave = threadIdx.x >> 6;
+    Team<MP, 1>& sh = lds.small[wave];
+    team_init(sh);
+    const int started = (int)gridDim.x * kWaves;
+    for (int q = nb + team_next(sh, &counter[1], true, (int)blockIdx.x * kWaves + wave, started);
+         q < ev.W; q = nb + team_next(sh, &counter[1], false, 0, started))
+      small_body(sh, (int64_t)ev.order[q]);
+  }
+}
+
+// ---------------------------------------------------------------- kernels
+
+template <int MP, int NW, bool GRAD>
+__device__ __forceinline__ void eval_one(Team<MP, NW>& sh, const Events& ev, int64_t w, int M,
+                                         const float* mu, const float* alpha, const float* beta,
+                                         double* ll, float* g_mu, float* g_alpha,
+                                         float* g_beta) {
+  constexpr int Q = Team<MP, NW>::Q;
+  const int t = team_tid<NW>();
+  if constexpr (GRAD) team_zero(sh);
+  team_load(sh, mu, alpha, beta, w, M);
+  const double Tw = ev.T[w];
+  team_eval<MP, NW, GRAD>(sh, ev.dt, ev.d, ev.begin[w], ev.n[w], Tw, ev.end_gap[w],
+                          ev.counts + w * M, M);
+  if (t == 0) ll[w] = sh.scal[0];
+  if constexpr (GRAD) {
+    if (t == 0) g_beta[w] = (float)sh.scal[1];
+    if (t < M) g_mu[w * M + t] = (float)(sh.gR64[t * Q + MP] - Tw);
+    for (int e = t; e < M * M; e += Team<MP, NW>::T) {
+      const int m = e / M, k = e % M;
+      g_alpha[w * M * M + e] = (float)(sh.gR64[m * Q + k] - sh.Cn[k]);
+    }
+  }
 }
 
 template <int MP, bool GRAD>
@@ -406,387 +667,414 @@ __global__ __launch_bounds__(kBlock) void lpc_eval_kernel(Events ev, int M, cons
                                                           double* ll, float* g_mu,
                                                           float* g_alpha, float* g_beta,
                                                           int* counter) {
-  __shared__ LpcWave<MP> slots[kWaves];
-  LpcWave<MP>& sh = slots[threadIdx.x >> 6];
-  lpc_init(sh);
-  constexpr int Q = LpcWave<MP>::Q;
-  const int lane = threadIdx.x & 63;
-  for (int q = lpc_next(counter, true); q < ev.W; q = lpc_next(counter, false)) {
-    const int64_t w = ev.order[q];
-    lpc_zero(sh);
-    lpc_load(sh, mu, alpha, beta, w, M);
-    const double T = ev.T[w];
-    lpc_eval<MP, GRAD>(sh, ev.dt, ev.d, ev.begin[w], ev.n[w], T, ev.end_gap[w],
-                       ev.counts + w * M, M);
-    if (lane == 0) ll[w] = sh.scal[0];
-    if constexpr (GRAD) {
-      if (lane == 0) g_beta[w] = (float)sh.scal[1];
-      if (lane < M) g_mu[w * M + lane] = (float)(sh.gR64[lane * Q + MP] - T);
-      for (int e = lane; e < M * M; e += 64) {
-        const int m = e / M, k = e % M;
-        g_alpha[w * M * M + e] = (float)(sh.gR64[m * Q + k] - sh.Cn[k]);
-      }
-    }
-  }
+  __shared__ BlockLds<MP> lds;
+  for_windows<MP>(
+      lds, ev, counter,
+      [&](Team<MP, kWaves>& sh, int64_t w) {
+        eval_one<MP, kWaves, GRAD>(sh, ev, w, M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta);
+      },
+      [&](Team<MP, 1>& sh, int64_t w) {
+        eval_one<MP, 1, GRAD>(sh, ev, w, M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta);
+      });
 }
 
-// Slot layout of the per-wave fits: lane l owns the alpha entries
-// e = l + 64 k (k < OWN, e = m * MP + n) and one extra slot k = OWN holding
-// mu_l (l < M) or beta (l == M).  Kinds: 0 none, 1 alpha, 2 mu, 3 beta.
-template <int MP>
+// Parameter slots of a team's fit: lane t owns the alpha entries
+// e = t + T k (k < OWN, e = m * MP + n) and one extra slot k = OWN holding
+// mu_t (t < M) or beta (t == M).  Kinds: 0 none, 1 alpha, 2 mu, 3 beta.
+template <int MP, int NW>
 struct Slots {
-  static constexpr int OWN = (MP * MP + 63) / 64;
+  static constexpr int T = 64 * NW;
+  static constexpr int OWN = (MP * MP + T - 1) / T;
   static constexpr int K = OWN + 1;
-  int M, lane, fix_beta;
+  int M, t, fix_beta;
   __device__ int kind(int k) const {
     if (k < OWN) {
-      const int e = lane + k * 64;
+      const int e = t + k * T;
       return (e < MP * MP && e / MP < M && e % MP < M) ? 1 : 0;
     }
-    if (lane < M) return 2;
-    if (lane == M) return fix_beta ? 0 : 3;
+    if (t < M) return 2;
+    if (t == M) return fix_beta ? 0 : 3;
     return 0;
   }
-  __device__ float get(const LpcWave<MP>& sh, int k) const {
+  __device__ float get(const Team<MP, NW>& sh, int k) const {
     const int kd = kind(k);
-    if (kd == 1) return sh.alpha[lane + k * 64];
-    if (kd == 2) return sh.mu[lane];
+    if (kd == 1) return sh.alpha[t + k * T];
+    if (kd == 2) return sh.mu[t];
     if (kd == 3) return sh.beta;
     return 0.f;
   }
-  __device__ void set(LpcWave<MP>& sh, int k, float v) const {
+  __device__ void set(Team<MP, NW>& sh, int k, float v) const {
     const int kd = kind(k);
-    if (kd == 1) sh.alpha[lane + k * 64] = v;
-    else if (kd == 2) sh.mu[lane] = v;
+    if (kd == 1) sh.alpha[t + k * T] = v;
+    else if (kd == 2) sh.mu[t] = v;
     else if (kd == 3) sh.beta = v;
   }
   // d ll / d theta of slot k after an evaluation with gradient.
-  __device__ double grad(const LpcWave<MP>& sh, int k, double T) const {
+  __device__ double grad(const Team<MP, NW>& sh, int k, double Tw) const {
+    constexpr int Q = Team<MP, NW>::Q;
     const int kd = kind(k);
     if (kd == 1) {
-      const int e = lane + k * 64;
-      return sh.gR64[(e / MP) * LpcWave<MP>::Q + e % MP] - sh.Cn[e % MP];
+      const int e = t + k * T;
+      return sh.gR64[(e / MP) * Q + e % MP] - sh.Cn[e % MP];
     }
-    if (kd == 2) return sh.gR64[lane * LpcWave<MP>::Q + MP] - T;
-    if (kd == 3) return sh.scal[1];
+    if (kd == 2) return sh.gR64[t * Q + MP] - Tw;
+    if (kd == 3) return uni(sh.scal[1]);
     return 0.0;
   }
 };
 
-template <int MP>
-__device__ __forceinline__ void lpc_store(const LpcWave<MP>& sh, int64_t w, int M, float* mu,
-                                          float* alpha, float* beta) {
-  const int lane = threadIdx.x & 63;
-  for (int e = lane; e < M * M; e += 64) alpha[w * M * M + e] = sh.alpha[(e / M) * MP + e % M];
-  if (lane < M) mu[w * M + lane] = sh.mu[lane];
-  if (lane == 0) beta[w] = sh.beta;
+template <int MP, int NW>
+__device__ __forceinline__ void team_store(Team<MP, NW>& sh, int64_t w, int M, float* mu,
+                                           float* alpha, float* beta) {
+  const int t = team_tid<NW>();
+  team_sync<NW>();
+  for (int e = t; e < M * M; e += Team<MP, NW>::T)
+    alpha[w * M * M + e] = sh.alpha[(e / M) * MP + e % M];
+  if (t < M) mu[w * M + t] = sh.mu[t];
+  if (t == 0) beta[w] = sh.beta;
 }
 
-// Persistent projected gradient ascent / projected Adam, one window per wave
-// (the rule of the workgroup kernel: evaluate, stop on a non-finite value,
-// on |delta ll| <= ll_tol max(|ll|, 1) or after max_steps updates, else step
+// Projected gradient ascent / projected Adam on one window (the rule of the
+// workgroup kernel: evaluate, stop on a non-finite value, on
+// |delta ll| <= ll_tol max(|ll|, 1) or after max_steps updates, else step
 // along the gradient divided by N and project).
+template <int MP, int NW>
+__device__ __forceinline__ void fit_one(Team<MP, NW>& sh, const Events& ev, int64_t w, int M,
+                                        const FitParams& o, float* mu, float* alpha, float* beta,
+                                        double* ll, int* steps, int* status, int* evals_out) {
+  constexpr int K = Slots<MP, NW>::K;
+  const int t = team_tid<NW>();
+  const Slots<MP, NW> sl{M, t, o.fix_beta};
+  team_load(sh, mu, alpha, beta, w, M);
+  const int n = ev.n[w];
+  const double Tw = ev.T[w];
+  const double rate = (double)max(n, 1) / Tw;
+  const double mu_min = o.mu_floor_rel * rate;
+  const double beta_min = o.beta_floor_rel * rate;
+  const double inv_n = 1.0 / (double)max(n, 1);
+  float m1[K], m2[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) m1[k] = m2[k] = 0.f;
+  double ll_prev = 0.0, b1t = 1.0, b2t = 1.0;
+  int s = 0, st = MDHP_FIT_MAX_STEPS;
+  for (s = 0;; ++s) {
+    team_zero(sh);
+    team_eval<MP, NW, true>(sh, ev.dt, ev.d, ev.begin[w], n, Tw, ev.end_gap[w],
+                            ev.counts + w * M, M);
+    const double l = uni(sh.scal[0]);
+    double g[K];
+    bool bad = !isfinite(l) || !isfinite(uni(sh.scal[1]));
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      g[k] = sl.grad(sh, k, Tw);
+      if (!isfinite(g[k])) bad = true;
+    }
+    if (team_any(sh, bad)) {
+      st = MDHP_FIT_NONFINITE;
+      break;
+    }
+    if (s >= 1 && fabs(l - ll_prev) <= o.ll_tol * fmax(fabs(l), 1.0)) {
+      st = MDHP_FIT_CONVERGED;
+      break;
+    }
+    if (s == o.max_steps) {
+      st = MDHP_FIT_MAX_STEPS;
+      break;
+    }
+    ll_prev = l;
+    b1t *= o.b1;
+    b2t *= o.b2;
+    const double bc1 = 1.0 - b1t, bc2 = 1.0 - b2t;
+    team_sync<NW>();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int kd = sl.kind(k);
+      if (kd == 0) continue;
+      const double gn = g[k] * inv_n;
+      double step;
+      if (o.optimizer == MDHP_OPT_PGD) {
+        step = o.lr * gn;
+      } else {
+        const double nm1 = o.b1 * (double)m1[k] + (1.0 - o.b1) * gn;
+        const double nm2 = o.b2 * (double)m2[k] + (1.0 - o.b2) * gn * gn;
+        m1[k] = (float)nm1;
+        m2[k] = (float)nm2;
+        step = o.lr * (nm1 / bc1) / (sqrt(nm2 / bc2) + o.eps);
+      }
+      const double lo = kd == 2 ? mu_min : (kd == 3 ? beta_min : 0.0);
+      sl.set(sh, k, (float)fmax((double)sl.get(sh, k) + step, lo));
+    }
+    team_colsum(sh, M);
+  }
+  // The parameters of the last evaluation are in LDS.
+  team_store(sh, w, M, mu, alpha, beta);
+  if (t == 0) {
+    ll[w] = sh.scal[0];
+    steps[w] = s;
+    status[w] = st;
+    if (evals_out) evals_out[w] = s + 1;
+  }
+}
+
 template <int MP>
 __global__ __launch_bounds__(kBlock) void lpc_fit_kernel(Events ev, int M, FitParams o,
                                                          float* mu, float* alpha, float* beta,
                                                          double* ll, int* steps, int* status,
                                                          int* evals_out, int* counter) {
-  __shared__ LpcWave<MP> slots[kWaves];
-  LpcWave<MP>& sh = slots[threadIdx.x >> 6];
-  lpc_init(sh);
-  constexpr int K = Slots<MP>::K;
-  const int lane = threadIdx.x & 63;
-  const Slots<MP> sl{M, lane, o.fix_beta};
-  for (int q = lpc_next(counter, true); q < ev.W; q = lpc_next(counter, false)) {
-    const int64_t w = ev.order[q];
-    lpc_load(sh, mu, alpha, beta, w, M);
-    const int n = ev.n[w];
-    const double T = ev.T[w];
-    const double rate = (double)max(n, 1) / T;
-    const double mu_min = o.mu_floor_rel * rate;
-    const double beta_min = o.beta_floor_rel * rate;
-    const double inv_n = 1.0 / (double)max(n, 1);
-    float m1[K], m2[K];
+  __shared__ BlockLds<MP> lds;
+  for_windows<MP>(
+      lds, ev, counter,
+      [&](Team<MP, kWaves>& sh, int64_t w) {
+        fit_one<MP, kWaves>(sh, ev, w, M, o, mu, alpha, beta, ll, steps, status, evals_out);
+      },
+      [&](Team<MP, 1>& sh, int64_t w) {
+        fit_one<MP, 1>(sh, ev, w, M, o, mu, alpha, beta, ll, steps, status, evals_out);
+      });
+}
+
+// Workspace floats of one team's L-BFGS fit: X, G, D, XN, then the S and Y
+// rings; K slots of T lanes each.
+template <int MP, int NW>
+constexpr int64_t team_ws() {
+  return (int64_t)(4 + 2 * kMaxHistory) * Slots<MP, NW>::K * 64 * NW;
+}
+
+// Per workgroup: the larger of one big team and kWaves small teams.
+template <int MP>
+constexpr int64_t block_ws() {
+  return team_ws<MP, kWaves>() > kWaves * team_ws<MP, 1>() ? team_ws<MP, kWaves>()
+                                                            : kWaves * team_ws<MP, 1>();
+}
+
+// Projected L-BFGS on one window: the rule of the workgroup kernel (two-loop
+// recursion on the free set, Armijo backtracking on the projected path,
+// curvature-checked history, restart from scaled steepest descent) with
+// team-level reductions.
+template <int MP, int NW>
+__device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, int64_t w, int M,
+                                          const FitParams& o, float* mu, float* alpha,
+                                          float* beta, double* ll, int* steps, int* status,
+                                          int* evals_out, float* base) {
+  constexpr int K = Slots<MP, NW>::K;
+  constexpr int T = Team<MP, NW>::T;
+  const int t = team_tid<NW>();
+  const int m_hist = o.history;
+  const Slots<MP, NW> sl{M, t, o.fix_beta};
+  auto X = [&](int k) -> float& { return base[(0 * K + k) * T + t]; };
+  auto Gv = [&](int k) -> float& { return base[(1 * K + k) * T + t]; };
+  auto Dv = [&](int k) -> float& { return base[(2 * K + k) * T + t]; };
+  auto XN = [&](int k) -> float& { return base[(3 * K + k) * T + t]; };
+  auto Sv = [&](int j, int k) -> float& { return base[((4 + j) * K + k) * T + t]; };
+  auto Yv = [&](int j, int k) -> float& {
+    return base[((4 + kMaxHistory + j) * K + k) * T + t];
+  };
+  team_load(sh, mu, alpha, beta, w, M);
+  const int n = ev.n[w];
+  const double Tw = ev.T[w];
+  const double rate = (double)max(n, 1) / Tw;
+  const float mu_min = (float)(o.mu_floor_rel * rate);
+  const float beta_min = (float)(o.beta_floor_rel * rate);
+  const double inv_n = 1.0 / (double)max(n, 1);
+  auto lower = [&](int k) -> float {
+    const int kd = sl.kind(k);
+    return kd == 2 ? mu_min : (kd == 3 ? beta_min : 0.f);
+  };
+  // Gradient of f = -ll / N for slot k, from the last evaluation in LDS.
+  auto gf = [&](int k) -> double { return -sl.grad(sh, k, Tw) * inv_n; };
+  // Evaluates at the LDS parameters; false if ll or any gradient entry is
+  // not finite.
+  auto evaluate = [&]() -> bool {
+    team_zero(sh);
+    team_eval<MP, NW, true>(sh, ev.dt, ev.d, ev.begin[w], n, Tw, ev.end_gap[w],
+                            ev.counts + w * M, M);
+    bool bad = !isfinite(uni(sh.scal[0])) || !isfinite(uni(sh.scal[1]));
 #pragma unroll
-    for (int k = 0; k < K; ++k) m1[k] = m2[k] = 0.f;
-    double ll_prev = 0.0, b1t = 1.0, b2t = 1.0;
-    int s = 0, st = MDHP_FIT_MAX_STEPS;
+    for (int k = 0; k < K; ++k)
+      if (!isfinite(gf(k))) bad = true;
+    return !team_any(sh, bad);
+  };
+  int nev = 1, st = MDHP_FIT_MAX_STEPS, s = 0, h = 0, head = 0;
+  double l = 0.0, sy_new = 0.0, yy_new = 0.0;
+  if (!evaluate()) {
+    st = MDHP_FIT_NONFINITE;
+    l = uni(sh.scal[0]);
+  } else {
+    l = uni(sh.scal[0]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      X(k) = sl.get(sh, k);
+      Gv(k) = (float)gf(k);
+    }
+    double f = -l * inv_n;
     for (s = 0;; ++s) {
-      lpc_zero(sh);
-      lpc_eval<MP, true>(sh, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], ev.counts + w * M,
-                         M);
-      const double l = sh.scal[0];
-      double g[K];
-      bool bad = !isfinite(l) || !isfinite(sh.scal[1]);
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        g[k] = sl.grad(sh, k, T);
-        if (!isfinite(g[k])) bad = true;
-      }
-      if (__any(bad)) {
-        st = MDHP_FIT_NONFINITE;
-        break;
-      }
-      if (s >= 1 && fabs(l - ll_prev) <= o.ll_tol * fmax(fabs(l), 1.0)) {
-        st = MDHP_FIT_CONVERGED;
-        break;
-      }
       if (s == o.max_steps) {
         st = MDHP_FIT_MAX_STEPS;
         break;
       }
-      ll_prev = l;
-      b1t *= o.b1;
-      b2t *= o.b2;
-      const double bc1 = 1.0 - b1t, bc2 = 1.0 - b2t;
-      wave_sync();
+      // Free gradient and its largest entry.
+      double qv[K], gmax_l = 0.0;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const int kd = sl.kind(k);
-        if (kd == 0) continue;
-        const double gn = g[k] * inv_n;
-        double step;
-        if (o.optimizer == MDHP_OPT_PGD) {
-          step = o.lr * gn;
-        } else {
-          const double nm1 = o.b1 * (double)m1[k] + (1.0 - o.b1) * gn;
-          const double nm2 = o.b2 * (double)m2[k] + (1.0 - o.b2) * gn * gn;
-          m1[k] = (float)nm1;
-          m2[k] = (float)nm2;
-          step = o.lr * (nm1 / bc1) / (sqrt(nm2 / bc2) + o.eps);
-        }
-        const double lo = kd == 2 ? mu_min : (kd == 3 ? beta_min : 0.0);
-        sl.set(sh, k, (float)fmax((double)sl.get(sh, k) + step, lo));
+        const float g = Gv(k);
+        const bool active = sl.kind(k) == 0 || (X(k) <= lower(k) && g > 0.f);
+        qv[k] = active ? 0.0 : (double)g;
+        gmax_l = fmax(gmax_l, fabs(qv[k]));
       }
-      lpc_colsum(sh, M);
+      const double gmax = team_max(sh, gmax_l);
+      if (gmax == 0.0) {
+        st = MDHP_FIT_CONVERGED;
+        break;
+      }
+      const double gamma0 = 0.01 / gmax;
+      for (int i = 0; i < h; ++i) {
+        const int j = (head - 1 - i + kMaxHistory) % kMaxHistory;
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) v += (double)Sv(j, k) * qv[k];
+        const double a = uni(sh.rho[j]) * team_sum(sh, v);
+        if (t == 0) sh.alf[j] = a;
+#pragma unroll
+        for (int k = 0; k < K; ++k) qv[k] -= a * (double)Yv(j, k);
+      }
+      const double gamma = h > 0 ? sy_new / yy_new : gamma0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) qv[k] *= gamma;
+      team_sync<NW>();
+      for (int i = h - 1; i >= 0; --i) {
+        const int j = (head - 1 - i + kMaxHistory) % kMaxHistory;
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) v += (double)Yv(j, k) * qv[k];
+        const double bcoef = uni(sh.rho[j]) * team_sum(sh, v);
+        const double a = uni(sh.alf[j]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) qv[k] += (a - bcoef) * (double)Sv(j, k);
+      }
+      double dg = 0.0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const float g = Gv(k);
+        const bool active = sl.kind(k) == 0 || (X(k) <= lower(k) && g > 0.f);
+        const double dk = active ? 0.0 : -qv[k];
+        Dv(k) = (float)dk;
+        dg += dk * (double)g;
+      }
+      dg = team_sum(sh, dg);
+      if (!(dg < 0.0)) {  // restart from scaled steepest descent
+        h = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float g = Gv(k);
+          const bool active = sl.kind(k) == 0 || (X(k) <= lower(k) && g > 0.f);
+          Dv(k) = active ? 0.f : (float)(-gamma0 * (double)g);
+        }
+      }
+      // Backtracking line search on the projected path.
+      double step = 1.0, ln = 0.0, fn = 0.0;
+      bool ok = false;
+      for (int ls = 0; ls < 20 && !ok; ++ls, step *= 0.5) {
+        double dec = 0.0;
+        team_sync<NW>();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          if (sl.kind(k) == 0) continue;
+          const float x0 = X(k);
+          const float xn = fmaxf((float)((double)x0 + step * (double)Dv(k)), lower(k));
+          XN(k) = xn;
+          sl.set(sh, k, xn);
+          dec += (double)Gv(k) * ((double)xn - (double)x0);
+        }
+        dec = team_sum(sh, dec);
+        team_colsum(sh, M);
+        const bool fin = evaluate();
+        ++nev;
+        ln = uni(sh.scal[0]);
+        fn = -ln * inv_n;
+        ok = fin && fn <= f + 1e-4 * dec;
+      }
+      if (!ok) {
+        st = MDHP_FIT_STALLED;
+        team_sync<NW>();
+#pragma unroll
+        for (int k = 0; k < K; ++k) sl.set(sh, k, X(k));
+        team_sync<NW>();
+        break;
+      }
+      double sy = 0.0, ss = 0.0, yy = 0.0;
+      float sk[K], yk[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const float gn = (float)gf(k);
+        const float xn = sl.kind(k) == 0 ? X(k) : XN(k);
+        sk[k] = xn - X(k);
+        yk[k] = gn - Gv(k);
+        sy += (double)sk[k] * (double)yk[k];
+        ss += (double)sk[k] * (double)sk[k];
+        yy += (double)yk[k] * (double)yk[k];
+        X(k) = xn;
+        Gv(k) = gn;
+      }
+      team_sum2(sh, sy, ss);
+      yy = team_sum(sh, yy);
+      if (sy > 1e-10 * sqrt(ss * yy)) {
+        if (h == m_hist) h -= 1;  // the oldest pair drops out of the ring
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          Sv(head, k) = sk[k];
+          Yv(head, k) = yk[k];
+        }
+        if (t == 0) sh.rho[head] = 1.0 / sy;
+        sy_new = sy;
+        yy_new = yy;
+        head = (head + 1) % kMaxHistory;
+        h += 1;
+        team_sync<NW>();
+      }
+      const double l_prev = l;
+      l = ln;
+      f = fn;
+      if (fabs(l - l_prev) <= o.ll_tol * fmax(fabs(l), 1.0)) {
+        st = MDHP_FIT_CONVERGED;
+        s += 1;
+        break;
+      }
     }
-    // The parameters of the last evaluation are in LDS.
-    lpc_store(sh, w, M, mu, alpha, beta);
-    if (lane == 0) {
-      ll[w] = sh.scal[0];
-      steps[w] = s;
-      status[w] = st;
-      if (evals_out) evals_out[w] = s + 1;
-    }
+  }
+  team_store(sh, w, M, mu, alpha, beta);
+  if (t == 0) {
+    ll[w] = l;
+    steps[w] = s;
+    status[w] = st;
+    if (evals_out) evals_out[w] = nev;
   }
 }
 
-// Workspace floats of one wave of the L-BFGS fit: X, G, D, XN, then the
-// S and Y rings; K slots of 64 lanes each.
-template <int MP>
-constexpr int64_t lpc_ws_per_wave() {
-  return (int64_t)(4 + 2 * kMaxHistory) * Slots<MP>::K * 64;
-}
-
-// Persistent projected L-BFGS, one window per wave: the rule of the
-// workgroup kernel (two-loop recursion on the free set, Armijo backtracking
-// on the projected path, curvature-checked history, restart from scaled
-// steepest descent) with wave-level reductions.
 template <int MP>
 __global__ __launch_bounds__(kBlock) void lpc_lbfgs_kernel(Events ev, int M, FitParams o,
                                                            float* mu, float* alpha, float* beta,
                                                            double* ll, int* steps, int* status,
                                                            int* evals_out, float* ws,
                                                            int* counter) {
-  __shared__ LpcWave<MP> slots[kWaves];
-  __shared__ double rho_s[kWaves][kMaxHistory], a_s[kWaves][kMaxHistory];
-  const int wave = threadIdx.x >> 6;
-  LpcWave<MP>& sh = slots[wave];
-  lpc_init(sh);
-  constexpr int K = Slots<MP>::K;
-  const int lane = threadIdx.x & 63;
-  const int m_hist = o.history;
-  const Slots<MP> sl{M, lane, o.fix_beta};
-  float* base = ws + (size_t)(blockIdx.x * kWaves + wave) * (size_t)lpc_ws_per_wave<MP>();
-  auto X = [&](int k) -> float& { return base[(0 * K + k) * 64 + lane]; };
-  auto Gv = [&](int k) -> float& { return base[(1 * K + k) * 64 + lane]; };
-  auto Dv = [&](int k) -> float& { return base[(2 * K + k) * 64 + lane]; };
-  auto XN = [&](int k) -> float& { return base[(3 * K + k) * 64 + lane]; };
-  auto Sv = [&](int j, int k) -> float& { return base[((4 + j) * K + k) * 64 + lane]; };
-  auto Yv = [&](int j, int k) -> float& {
-    return base[((4 + kMaxHistory + j) * K + k) * 64 + lane];
-  };
-  for (int q = lpc_next(counter, true); q < ev.W; q = lpc_next(counter, false)) {
-    const int64_t w = ev.order[q];
-    lpc_load(sh, mu, alpha, beta, w, M);
-    const int n = ev.n[w];
-    const double T = ev.T[w];
-    const double rate = (double)max(n, 1) / T;
-    const float mu_min = (float)(o.mu_floor_rel * rate);
-    const float beta_min = (float)(o.beta_floor_rel * rate);
-    const double inv_n = 1.0 / (double)max(n, 1);
-    auto lower = [&](int k) -> float {
-      const int kd = sl.kind(k);
-      return kd == 2 ? mu_min : (kd == 3 ? beta_min : 0.f);
-    };
-    // Gradient of f = -ll / N per slot; false if ll or any entry is not finite.
-    double gf[K];
-    auto evaluate = [&]() -> bool {
-      lpc_zero(sh);
-      lpc_eval<MP, true>(sh, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], ev.counts + w * M,
-                         M);
-      bool bad = !isfinite(sh.scal[0]) || !isfinite(sh.scal[1]);
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        gf[k] = -sl.grad(sh, k, T) * inv_n;
-        if (!isfinite(gf[k])) bad = true;
-      }
-      return !__any(bad);
-    };
-    int nev = 1, st = MDHP_FIT_MAX_STEPS, s = 0, h = 0, head = 0;
-    double l = 0.0, sy_new = 0.0, yy_new = 0.0;
-    if (!evaluate()) {
-      st = MDHP_FIT_NONFINITE;
-      l = sh.scal[0];
-    } else {
-      l = sh.scal[0];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        X(k) = sl.get(sh, k);
-        Gv(k) = (float)gf[k];
-      }
-      double f = -l * inv_n;
-      for (s = 0;; ++s) {
-        if (s == o.max_steps) {
-          st = MDHP_FIT_MAX_STEPS;
-          break;
-        }
-        // Free gradient and its largest entry.
-        double qv[K], gmax_l = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float g = Gv(k);
-          const bool active = sl.kind(k) == 0 || (X(k) <= lower(k) && g > 0.f);
-          qv[k] = active ? 0.0 : (double)g;
-          gmax_l = fmax(gmax_l, fabs(qv[k]));
-        }
-        const double gmax = wave_max(gmax_l);
-        if (gmax == 0.0) {
-          st = MDHP_FIT_CONVERGED;
-          break;
-        }
-        const double gamma0 = 0.01 / gmax;
-        for (int i = 0; i < h; ++i) {
-          const int j = (head - 1 - i + kMaxHistory) % kMaxHistory;
-          double v = 0.0;
-#pragma unroll
-          for (int k = 0; k < K; ++k) v += (double)Sv(j, k) * qv[k];
-          const double a = rho_s[wave][j] * wave_sum(v);
-          a_s[wave][j] = a;  // every lane writes the same value
-#pragma unroll
-          for (int k = 0; k < K; ++k) qv[k] -= a * (double)Yv(j, k);
-        }
-        const double gamma = h > 0 ? sy_new / yy_new : gamma0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) qv[k] *= gamma;
-        for (int i = h - 1; i >= 0; --i) {
-          const int j = (head - 1 - i + kMaxHistory) % kMaxHistory;
-          double v = 0.0;
-#pragma unroll
-          for (int k = 0; k < K; ++k) v += (double)Yv(j, k) * qv[k];
-          const double bcoef = rho_s[wave][j] * wave_sum(v);
-          const double a = a_s[wave][j];
-#pragma unroll
-          for (int k = 0; k < K; ++k) qv[k] += (a - bcoef) * (double)Sv(j, k);
-        }
-        double dg = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float g = Gv(k);
-          const bool active = sl.kind(k) == 0 || (X(k) <= lower(k) && g > 0.f);
-          const double dk = active ? 0.0 : -qv[k];
-          Dv(k) = (float)dk;
-          dg += dk * (double)g;
-        }
-        dg = wave_sum(dg);
-        if (!(dg < 0.0)) {  // restart from scaled steepest descent
-          h = 0;
-#pragma unroll
-          for (int k = 0; k < K; ++k) {
-            const float g = Gv(k);
-            const bool active = sl.kind(k) == 0 || (X(k) <= lower(k) && g > 0.f);
-            Dv(k) = active ? 0.f : (float)(-gamma0 * (double)g);
-          }
-        }
-        // Backtracking line search on the projected path.
-        double t = 1.0, ln = 0.0, fn = 0.0;
-        bool ok = false;
-        for (int ls = 0; ls < 20 && !ok; ++ls, t *= 0.5) {
-          double dec = 0.0;
-          wave_sync();
-#pragma unroll
-          for (int k = 0; k < K; ++k) {
-            if (sl.kind(k) == 0) continue;
-            const float x0 = X(k);
-            const float xn = fmaxf((float)((double)x0 + t * (double)Dv(k)), lower(k));
-            XN(k) = xn;
-            sl.set(sh, k, xn);
-            dec += (double)Gv(k) * ((double)xn - (double)x0);
-          }
-          dec = wave_sum(dec);
-          lpc_colsum(sh, M);
-          const bool fin = evaluate();
-          ++nev;
-          ln = sh.scal[0];
-          fn = -ln * inv_n;
-          ok = fin && fn <= f + 1e-4 * dec;
-        }
-        if (!ok) {
-          st = MDHP_FIT_STALLED;
-          wave_sync();
-#pragma unroll
-          for (int k = 0; k < K; ++k) sl.set(sh, k, X(k));
-          wave_sync();
-          break;
-        }
-        double sy = 0.0, ss = 0.0, yy = 0.0;
-        float sk[K], yk[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float gn = (float)gf[k];
-          const float xn = sl.kind(k) == 0 ? X(k) : XN(k);
-          sk[k] = xn - X(k);
-          yk[k] = gn - Gv(k);
-          sy += (double)sk[k] * (double)yk[k];
-          ss += (double)sk[k] * (double)sk[k];
-          yy += (double)yk[k] * (double)yk[k];
-          X(k) = xn;
-          Gv(k) = gn;
-        }
-        sy = wave_sum(sy);
-        ss = wave_sum(ss);
-        yy = wave_sum(yy);
-        if (sy > 1e-10 * sqrt(ss * yy)) {
-          if (h == m_hist) h -= 1;  // the oldest pair drops out of the ring
-#pragma unroll
-          for (int k = 0; k < K; ++k) {
-            Sv(head, k) = sk[k];
-            Yv(head, k) = yk[k];
-          }
-          rho_s[wave][head] = 1.0 / sy;  // every lane writes the same value
-          sy_new = sy;
-          yy_new = yy;
-          head = (head + 1) % kMaxHistory;
-          h += 1;
-        }
-        const double l_prev = l;
-        l = ln;
-        f = fn;
-        if (fabs(l - l_prev) <= o.ll_tol * fmax(fabs(l), 1.0)) {
-          st = MDHP_FIT_CONVERGED;
-          s += 1;
-          break;
-        }
-      }
-    }
-    lpc_store(sh, w, M, mu, alpha, beta);
-    if (lane == 0) {
-      ll[w] = l;
-      steps[w] = s;
-      status[w] = st;
-      if (evals_out) evals_out[w] = nev;
-    }
-  }
+  __shared__ BlockLds<MP> lds;
+  float* blk = ws + (size_t)blockIdx.x * (size_t)block_ws<MP>();
+  for_windows<MP>(
+      lds, ev, counter,
+      [&](Team<MP, kWaves>& sh, int64_t w) {
+        lbfgs_one<MP, kWaves>(sh, ev, w, M, o, mu, alpha, beta, ll, steps, status, evals_out,
+                              blk);
+      },
+      [&](Team<MP, 1>& sh, int64_t w) {
+        lbfgs_one<MP, 1>(sh, ev, w, M, o, mu, alpha, beta, ll, steps, status, evals_out,
+                         blk + (size_t)(threadIdx.x >> 6) * (size_t)team_ws<MP, 1>());
+      });
+}
+
+// Grid: enough workgroups for the big windows and the waves for the rest,
+// at most what fits on the device at once.
+template <class KERN>
+int lpc_grid(KERN k, int64_t W, int64_t n_big) {
+  const int64_t want = std::max<int64_t>(n_big, (W - n_big + kWaves - 1) / kWaves);
+  return occupancy_grid(k, kBlock, std::max<int64_t>(want, 1));
 }
 
 template <int MP>
@@ -795,15 +1083,14 @@ hipError_t launch_lpc_eval(const Events& ev, int M, const float* mu, const float
                            float* g_beta, int* counter, hipStream_t s, bool grad) {
   if (ev.W == 0) return hipSuccess;
   reset_counter(counter, s);
-  const int64_t groups = (ev.W + kWaves - 1) / kWaves;
   if (grad) {
     auto k = lpc_eval_kernel<MP, true>;
-    hipLaunchKernelGGL(k, dim3(occupancy_grid(k, kBlock, groups)), dim3(kBlock), 0, s, ev, M, mu,
-                       alpha, beta, ll, g_mu, g_alpha, g_beta, counter);
+    hipLaunchKernelGGL(k, dim3(lpc_grid(k, ev.W, ev.n_big)), dim3(kBlock), 0, s, ev, M, mu, alpha, beta, ll,
+                       g_mu, g_alpha, g_beta, counter);
   } else {
     auto k = lpc_eval_kernel<MP, false>;
-    hipLaunchKernelGGL(k, dim3(occupancy_grid(k, kBlock, groups)), dim3(kBlock), 0, s, ev, M, mu,
-                       alpha, beta, ll, g_mu, g_alpha, g_beta, counter);
+    hipLaunchKernelGGL(k, dim3(lpc_grid(k, ev.W, ev.n_big)), dim3(kBlock), 0, s, ev, M, mu, alpha, beta, ll,
+                       g_mu, g_alpha, g_beta, counter);
   }
   return hipGetLastError();
 }
@@ -814,26 +1101,23 @@ hipError_t launch_lpc_fit(const Events& ev, int M, const FitParams& o, float* mu
                           int64_t ws_floats, int* counter, hipStream_t s) {
   if (ev.W == 0) return hipSuccess;
   reset_counter(counter, s);
-  const int64_t groups = (ev.W + kWaves - 1) / kWaves;
   if (o.optimizer == MDHP_OPT_LBFGS) {
     auto k = lpc_lbfgs_kernel<MP>;
-    const int grid = (int)std::min<int64_t>(occupancy_grid(k, kBlock, groups),
-                                            ws_floats / (kWaves * lpc_ws_per_wave<MP>()));
+    const int grid = (int)std::min<int64_t>(lpc_grid(k, ev.W, ev.n_big), ws_floats / block_ws<MP>());
     if (grid < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), 0, s, ev, M, o, mu, alpha, beta, ll, steps,
                        status, evals, ws, counter);
     return hipGetLastError();
   }
   auto k = lpc_fit_kernel<MP>;
-  hipLaunchKernelGGL(k, dim3(occupancy_grid(k, kBlock, groups)), dim3(kBlock), 0, s, ev, M, o, mu,
-                     alpha, beta, ll, steps, status, evals, counter);
+  hipLaunchKernelGGL(k, dim3(lpc_grid(k, ev.W, ev.n_big)), dim3(kBlock), 0, s, ev, M, o, mu, alpha, beta, ll,
+                     steps, status, evals, counter);
   return hipGetLastError();
 }
 
 template <int MP>
-int64_t lpc_ws(int64_t W) {
-  const int64_t groups = std::max<int64_t>((W + kWaves - 1) / kWaves, 1);
-  return kWaves * lpc_ws_per_wave<MP>() * occupancy_grid(lpc_lbfgs_kernel<MP>, kBlock, groups);
+int64_t lpc_ws(int64_t W, int64_t n_big) {
+  return block_ws<MP>() * lpc_grid(lpc_lbfgs_kernel<MP>, W, n_big);
 }
 
 int mp_for(int M) { return M <= 4 ? 4 : (M <= 8 ? 8 : 16); }
@@ -860,11 +1144,11 @@ hipError_t lpc_fit(const Events& ev, int M, const FitParams& o, float* mu, float
   }
 }
 
-int64_t lpc_lbfgs_workspace(int M, int64_t W) {
+int64_t lpc_lbfgs_workspace(int M, int64_t W, int64_t n_big) {
   switch (mp_for(M)) {
-    case 4: return lpc_ws<4>(W);
-    case 8: return lpc_ws<8>(W);
-    default: return lpc_ws<16>(W);
+    case 4: return lpc_ws<4>(W, n_big);
+    case 8: return lpc_ws<8>(W, n_big);
+    default: return lpc_ws<16>(W, n_big);
   }
 }
 
