@@ -97,11 +97,14 @@ typedef struct mdhp_batch {
 
 /* Options of mdhp_fit_batch.  All rules work on f = -ll / max(N_w, 1) with
  * the projection Proj: mu >= mu_floor_rel * r_w, alpha >= 0,
- * beta >= beta_floor_rel * r_w, where r_w = max(N_w, 1) / T_w.
+ * beta >= beta_floor_rel * r_w, where r_w = max(N_w, 1) / T_w.  Likelihood
+ * changes are measured against max(|ll|, N_w, 1): at the optimum the
+ * compensator equals N_w (lambda is linear in (mu, alpha)), so N_w is the
+ * likelihood's own scale even where ll itself is close to 0.
  *
  * PGD / PADAM: step s = 0, 1, ... evaluates ll_s and its gradient g_s at
  * theta_s; the window stops as converged when s >= 1 and
- * |ll_s - ll_{s-1}| <= ll_tol * max(|ll_s|, 1), stops as MAX_STEPS when
+ * |ll_s - ll_{s-1}| <= ll_tol * max(|ll_s|, N_w, 1), stops as MAX_STEPS when
  * s == max_steps, and otherwise moves to
  *   theta_{s+1} = Proj(theta_s + step(g_s / max(N_w, 1)))
  * with step = lr * g (PGD) or the bias-corrected Adam step (PADAM).
@@ -115,7 +118,7 @@ typedef struct mdhp_batch {
  * trials, each a likelihood + gradient evaluation) whose projected point
  * satisfies f(x') <= f(x) + 1e-4 g.(x' - x); a pair enters the history if
  * s.y > 1e-10 |s| |y|.  The window stops as converged when an accepted step
- * changes ll by at most ll_tol * max(|ll|, 1) or the free gradient is zero,
+ * changes ll by at most ll_tol * max(|ll|, N_w, 1) or the free gradient is zero,
  * as MAX_STEPS after max_steps accepted steps, and as STALLED when no trial
  * is accepted.  lr, adam_* are not used. */
 typedef struct mdhp_fit_opts {
@@ -175,6 +178,15 @@ mdhp_status mdhp_grad(mdhp_plan* plan, const float* mu, const float* alpha, cons
 mdhp_status mdhp_fit_batch(mdhp_plan* plan, const mdhp_fit_opts* opts, float* mu, float* alpha,
                            float* beta, double* ll, int32_t* steps, int32_t* status,
                            int32_t* evals, void* stream);
+
+/* Cold start of every window (the initial point of the fits and the warm
+ * start's fallback; the paper leaves the initial point of its solver open,
+ * so this is a stated choice): mu_m = 0.5 max(N_m, 0.5) / T_w (half the
+ * window's rate of dimension m, N_m its events), beta = 1 (every entry in
+ * per-pair mode) and alpha_mn = 0.5 / M, a branching matrix of spectral
+ * radius 0.5.  mu [W][M], alpha [W][M][M], beta [W] or [W][M][M] are device
+ * memory owned by the caller.  Enqueued on stream. */
+mdhp_status mdhp_cold_start(mdhp_plan* plan, float* mu, float* alpha, float* beta, void* stream);
 
 /* Checks parameter values on the device (mu > 0, alpha >= 0, beta > 0, all
  * finite) and returns MDHP_E_PARAM if any window violates them.

@@ -356,7 +356,7 @@ struct FitOpts {
 // + gradient evaluation) is the first whose projected point satisfies
 // f(x') <= f(x) + 1e-4 g.(x' - x); the pair (x' - x, g' - g) enters the
 // history if its curvature s.y exceeds 1e-10 |s| |y|.  Stops as converged
-// when |ll' - ll| <= ll_tol max(|ll'|, 1) after an accepted step (or when
+// when |ll' - ll| <= ll_tol max(|ll'|, N, 1) after an accepted step (or when
 // the free gradient vanishes), as MAX_STEPS after max_steps accepted steps,
 // and as STALLED (3) when no trial step is accepted.
 struct LbfgsResult {
@@ -472,7 +472,8 @@ LbfgsResult lbfgs_fit(std::vector<double>& x, const std::vector<double>& lb,
     const double l_prev = l;
     l = ln;
     f = fn;
-    if (std::fabs(l - l_prev) <= o.ll_tol * std::max(std::fabs(l), 1.0)) return {s + 1, 0, evals, l};
+    if (std::fabs(l - l_prev) <= o.ll_tol * std::max(std::fabs(l), 1.0 / inv_n))
+      return {s + 1, 0, evals, l};
   }
 }
 
@@ -518,7 +519,7 @@ int mdhp_oracle_grad_brute(const int64_t* offsets, const double* t, const int32_
 
 // Projected gradient ascent per window.  Step s = 0, 1, ...: evaluate ll_s
 // and the gradient g_s at theta_s (recursion form); stop as converged when
-// s >= 1 and |ll_s - ll_{s-1}| <= ll_tol * max(|ll_s|, 1); stop as not
+// s >= 1 and |ll_s - ll_{s-1}| <= ll_tol * max(|ll_s|, N, 1); stop as not
 // converged when s == max_steps; otherwise theta_{s+1} = Proj(theta_s +
 // step(g_s / max(N, 1))).  The returned theta is theta_s with ll_s, and
 // steps[w] = s (the number of updates applied), evals[w] (optional) the
@@ -629,7 +630,7 @@ int mdhp_oracle_fit(const int64_t* offsets, const double* t, const int32_t* dim,
       }
       th_eval = th;
       ll_eval = l;
-      if (s >= 1 && std::fabs(l - ll_prev) <= o.ll_tol * std::max(std::fabs(l), 1.0)) {
+      if (s >= 1 && std::fabs(l - ll_prev) <= o.ll_tol * std::max(std::fabs(l), 1.0 / inv_n)) {
         st = 0;
         break;
       }

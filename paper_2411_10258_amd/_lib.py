@@ -22,7 +22,7 @@ EXPORTS = (
     "mdhp_surrogate_destroy", "mdhp_surrogate_num_params", "mdhp_surrogate_get_weights",
     "mdhp_surrogate_set_weights", "mdhp_surrogate_forward", "mdhp_surrogate_get_hidden",
     "mdhp_surrogate_backward", "mdhp_surrogate_get_gradients", "mdhp_surrogate_adam",
-    "mdhp_surrogate_train_step", "mdhp_warm_start",
+    "mdhp_surrogate_train_step", "mdhp_warm_start", "mdhp_cold_start",
 )
 
 MDHP_OK = 0
@@ -80,6 +80,7 @@ def load() -> ctypes.CDLL:
     lib.mdhp_grad.argtypes = [P, P, P, P, P, P, P, P, P]
     lib.mdhp_fit_batch.argtypes = [P, ctypes.POINTER(MdhpFitOpts), P, P, P, P, P, P, P, P]
     lib.mdhp_check_params.argtypes = [P, P, P, P, P]
+    lib.mdhp_cold_start.argtypes = [P, P, P, P, P]
     lib.mdhp_features.argtypes = [ctypes.POINTER(MdhpBatch), I32, I32, P, P]
     lib.mdhp_surrogate_create.argtypes = [I32, I32, I32, I32, ctypes.c_uint64, ctypes.POINTER(P)]
     lib.mdhp_surrogate_destroy.argtypes = [P]

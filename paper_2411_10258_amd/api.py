@@ -17,7 +17,7 @@ from ._lib import (BETA_PAIR, BETA_SHARED, FIT_CONVERGED, FIT_MAX_STEPS, FIT_NON
                    FIT_STALLED, OPT_LBFGS, OPT_PADAM, OPT_PGD, MdhpError)
 
 __all__ = ["Plan", "FitOptions", "mdhp_plan_create", "mdhp_plan_destroy", "mdhp_loglik",
-           "mdhp_grad", "mdhp_fit_batch", "mdhp_check_params", "mdhp_status_string",
+           "mdhp_grad", "mdhp_fit_batch", "mdhp_check_params", "mdhp_cold_start", "mdhp_status_string",
            "BETA_SHARED", "BETA_PAIR", "OPT_PGD", "OPT_PADAM", "OPT_LBFGS", "FIT_CONVERGED",
            "FIT_MAX_STEPS", "FIT_NONFINITE", "FIT_STALLED", "MdhpError"]
 
@@ -107,6 +107,11 @@ def mdhp_fit_batch(handle, opts: FitOptions, mu, alpha, beta, ll, steps, status,
                                           ctypes.c_void_p(_stream(stream))))
 
 
+def mdhp_cold_start(handle, mu, alpha, beta, stream=None) -> None:
+    _lib.check(_lib.load().mdhp_cold_start(ctypes.c_void_p(handle), _ptr(mu), _ptr(alpha),
+                                           _ptr(beta), ctypes.c_void_p(_stream(stream))))
+
+
 def mdhp_check_params(handle, mu, alpha, beta, stream=None) -> None:
     _lib.check(_lib.load().mdhp_check_params(ctypes.c_void_p(handle), _ptr(mu), _ptr(alpha),
                                              _ptr(beta), ctypes.c_void_p(_stream(stream))))
@@ -181,6 +186,16 @@ class Plan:
         if return_evals:
             return mu, alpha, beta, ll, steps, status, evals
         return mu, alpha, beta, ll, steps, status
+
+    def cold_start(self, stream=None):
+        """The cold start (mu, alpha, beta) of every window, on the device."""
+        W, M = self.W, self.M
+        mu = torch.empty((W, M), dtype=torch.float32, device=self.device)
+        alpha = torch.empty((W, M, M), dtype=torch.float32, device=self.device)
+        beta = torch.empty((W,) if self.beta_mode == BETA_SHARED else (W, M, M),
+                           dtype=torch.float32, device=self.device)
+        mdhp_cold_start(self.handle, mu, alpha, beta, stream)
+        return mu, alpha, beta
 
     def check_params(self, mu, alpha, beta, stream=None) -> None:
         mu, alpha, beta = self._params(mu, alpha, beta)

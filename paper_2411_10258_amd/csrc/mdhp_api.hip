@@ -22,7 +22,7 @@ struct mdhp_plan {
   double* T = nullptr;
   float* end_gap = nullptr;
   int32_t* order = nullptr;
-  int32_t* counts = nullptr;  // [W][M] events per dimension (lane-major plans)
+  int32_t* counts = nullptr;  // [W][M] events per dimension
   int* counter = nullptr;  // window queue heads [2]
   int64_t n_big = 0;       // lane-major: windows run by a whole workgroup
   int* flags = nullptr;    // [0] error bits of prepare / check_params
@@ -115,6 +115,21 @@ __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double
       Tc[w] = Tw;
     }
     if (err) atomicOr(flags, err);
+  }
+}
+
+// Cold start (see mdhp_cold_start): one thread per parameter entry.
+__global__ void cold_start_kernel(const int32_t* __restrict__ counts, const double* __restrict__ T,
+                                  int64_t W, int M, int pair, float* mu, float* alpha,
+                                  float* beta) {
+  const int64_t MM = (int64_t)M * M;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < W * MM; i += stride) {
+    const int64_t w = i / MM, e = i % MM;
+    alpha[i] = (float)(0.5 / M);
+    if (pair) beta[i] = 1.f;
+    else if (e == 0) beta[w] = 1.f;
+    if (e < M) mu[w * M + e] = (float)(0.5 * fmax((double)counts[w * M + e], 0.5) / T[w]);
   }
 }
 
@@ -267,7 +282,7 @@ mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, 
       (e = dev_alloc(&p->begin, W)) != hipSuccess || (e = dev_alloc(&p->n, W)) != hipSuccess ||
       (e = dev_alloc(&p->T, W)) != hipSuccess || (e = dev_alloc(&p->end_gap, W)) != hipSuccess ||
       (e = dev_alloc(&p->order, W)) != hipSuccess ||
-      (p->lane_major && (e = dev_alloc(&p->counts, W * M)) != hipSuccess) ||
+      (e = dev_alloc(&p->counts, W * M)) != hipSuccess ||
       (e = dev_alloc(&p->counter, 2)) != hipSuccess ||
       (e = dev_alloc(&p->flags, 1)) != hipSuccess ||
       (e = dev_alloc(&p->ll_ws, 2 * W)) != hipSuccess ||
@@ -413,6 +428,19 @@ mdhp_status mdhp_warm_start(mdhp_plan* p, const float* pred, const float* mean,
     e = choose_init(ll_w, ll_c, p->W, p->M, mu_cold, alpha_cold, beta_cold, mu, alpha, beta,
                     used_warm, s);
   if (e != hipSuccess) return hip_fail(e, "warm_start");
+  return MDHP_OK;
+}
+
+mdhp_status mdhp_cold_start(mdhp_plan* p, float* mu, float* alpha, float* beta, void* stream) {
+  if (!plan_ok(p)) return fail(MDHP_E_INVAL, "cold_start: invalid plan");
+  if (p->W == 0) return MDHP_OK;
+  if (!mu || !alpha || !beta) return fail(MDHP_E_INVAL, "cold_start: null pointer");
+  const int64_t n = p->W * p->M * p->M;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(cold_start_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, p->counts,
+                     p->T, p->W, p->M, p->beta_mode == MDHP_BETA_PAIR ? 1 : 0, mu, alpha, beta);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "cold_start: launch");
   return MDHP_OK;
 }
 

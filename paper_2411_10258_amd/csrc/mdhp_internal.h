@@ -39,7 +39,7 @@ struct Events {
   const double* T;       // [W] window lengths
   const float* end_gap;  // [W] T - t_last (T for an empty window), FP64-computed
   const int32_t* order;  // [W] window ids, largest first
-  const int32_t* counts; // [W][M] events per dimension (lane-major plans only, else null)
+  const int32_t* counts; // [W][M] events per dimension
   int64_t n_big;         // lane-major plans: windows of >= kBigWindow events (a prefix of order)
 };
 
@@ -77,7 +77,7 @@ inline void reset_counter(int* counter, hipStream_t s) {
 constexpr int kLaneMajorMaxM = MDHP_LANE_MAJOR_MAX_M;
 // Lane-major windows of at least this many events are laid out for, and
 // run by, a whole workgroup (256 chunks); shorter ones by one wavefront (64).
-constexpr int64_t kBigWindow = 4096;
+constexpr int64_t kBigWindow = 1024;
 __host__ __device__ inline int64_t lane_team(int64_t n) { return n >= kBigWindow ? kBlock : 64; }
 
 // Lane-major (one chunk per lane, one window per wave) kernels, M <= 16.

@@ -54,17 +54,41 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- wave level
 
-template <class F>
-__device__ __forceinline__ F wave_sum(F v) {
-#pragma unroll
-  for (int k = 32; k > 0; k >>= 1) v += __shfl_xor(v, k, 64);
-  return v;
+// v of another lane of the same 16-lane row by a DPP lane map (both halves
+// of the double moved).
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double,
+                            ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double lane64(double v, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum (or max) over the wave in a fixed order: butterflies inside each
+// 16-lane row by DPP (xor 1, xor 2, then the row's half and full mirrors),
+// then the four row totals read as scalars.  The result is uniform.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp64<0x141>(v);  // row_half_mirror
+  v += dpp64<0x140>(v);  // row_mirror
+  return (lane64(v, 0) + lane64(v, 16)) + (lane64(v, 32) + lane64(v, 48));
 }
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int k = 32; k > 0; k >>= 1) v = fmax(v, __shfl_xor(v, k, 64));
-  return v;
+  v = fmax(v, dpp64<0xB1>(v));
+  v = fmax(v, dpp64<0x4E>(v));
+  v = fmax(v, dpp64<0x141>(v));
+  v = fmax(v, dpp64<0x140>(v));
+  return fmax(fmax(lane64(v, 0), lane64(v, 16)), fmax(lane64(v, 32), lane64(v, 48)));
 }
 
 // A value every lane of the wave holds, moved to a scalar register (the
@@ -152,12 +176,20 @@ struct alignas(16) Team {
   static constexpr int Q = MP + 1;   // row stride of gR64: G_R[m][0..MP-1], Gmu[m]
   static constexpr int T = 64 * NW;  // lanes (= chunks) of the team
   static constexpr int XC = 3 * MP + 4;
-  float alpha[MP * MP];              // [m * MP + n], zero outside M x M
+  // LDS strides chosen against bank conflicts (32 banks of 4 bytes): rows of
+  // alpha start in distinct bank quads for 8 consecutive targets, so that
+  // 16-byte row gathers by 8 lanes with different targets do not collide;
+  // staging columns are 68 floats apart, so that 8 lanes reading 16 bytes
+  // each from 8 columns cover all 32 banks once.
+  static constexpr int AS = MP == 4 ? 4 : MP + 4;  // alpha row stride
+  static constexpr int VS = 68;                    // staging column stride
+  static constexpr int GS = 65;                    // per-lane Gmu row stride
+  float alpha[MP * AS];              // [m * AS + n], zero outside M x M
   float mu[MP];                      // zero outside M
   float colsum[MP];                  // sum_m alpha_mn
-  float vst[NW][MP * 64];            // per wave: step staging, w_k R_n(k) at [n * 64 + k]
-  float hot[NW][16 * 64];            // per wave: 1 at [d_k * 64 + k] during a step, else 0
-  float gmu[NW][64 * Q];             // per lane: sum of w over its events of target m
+  float vst[NW][MP * VS];            // per wave: step staging, w_k R_n(k) at [n * VS + k]
+  float hot[NW][16 * VS];            // per wave: 1 at [d_k * VS + k] during a step, else 0
+  float gmu[NW][MP * GS];            // per lane k: sum of w over its events of target m, [m * GS + k]
   double gpart[NW][MP * MP + MP];    // per wave: FP64 G_R (MFMA spans) and Gmu partials
   float xc[NW][XC];                  // per wave: its inclusive total (R, S, P, A, D, F), then
                                      // the carry of the team's earlier waves
@@ -241,7 +273,7 @@ __device__ __forceinline__ bool team_any(Team<MP, NW>& sh, bool bad) {
 // in two independent accumulator chains.  Lane l supplies A = H[16q + s][l % 16]
 // and B = V[16q + s][l % 16] (q = l / 16) to instruction s, and holds
 // G_R[4q + r][l % 16] in acc0[r] + acc1[r].
-template <int MP>
+template <int MP, int VS>
 __device__ __forceinline__ void step_outer(const float* vst, const float* hot, f32x4& acc0,
                                            f32x4& acc1) {
   const int lane = threadIdx.x & 63;
@@ -249,8 +281,8 @@ __device__ __forceinline__ void step_outer(const float* vst, const float* hot, f
   f32x4 a[4], b[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    a[i] = *reinterpret_cast<const f32x4*>(&hot[col * 64 + base + 4 * i]);
-    b[i] = col < MP ? *reinterpret_cast<const f32x4*>(&vst[(col % MP) * 64 + base + 4 * i])
+    a[i] = *reinterpret_cast<const f32x4*>(&hot[col * VS + base + 4 * i]);
+    b[i] = col < MP ? *reinterpret_cast<const f32x4*>(&vst[(col % MP) * VS + base + 4 * i])
                     : f32x4{0.f, 0.f, 0.f, 0.f};
   }
 #pragma unroll
@@ -259,6 +291,39 @@ __device__ __forceinline__ void step_outer(const float* vst, const float* hot, f
     acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][1], b[i][1], acc1, 0, 0, 0);
     acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][2], b[i][2], acc0, 0, 0, 0);
     acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][3], b[i][3], acc1, 0, 0, 0);
+  }
+}
+
+// Runs body(j, dt_j, d_j) for the steps j = 0 .. c-1 of a lane's chunk
+// (slot stride T), with the loads of the next kAhead steps in flight.
+constexpr int kAhead = 4;
+template <int T, class BODY>
+__device__ __forceinline__ void for_steps(const float* __restrict__ dtw,
+                                          const uint8_t* __restrict__ dw, int c, BODY&& body) {
+  float dt_c[kAhead];
+  int d_c[kAhead];
+  auto load = [&](int j0, float (&dtq)[kAhead], int (&dq)[kAhead]) {
+    static_for<kAhead>([&](auto Q) {
+      constexpr int q = decltype(Q)::value;
+      const bool in = j0 + q < c;  // uniform
+      dtq[q] = in ? dtw[(int64_t)(j0 + q) * T] : 0.f;
+      dq[q] = in ? (int)dw[(int64_t)(j0 + q) * T] : kPad;
+    });
+  };
+  load(0, dt_c, d_c);
+  for (int jb = 0; jb < c; jb += kAhead) {
+    float dt_n[kAhead];
+    int d_n[kAhead];
+    load(jb + kAhead, dt_n, d_n);
+    static_for<kAhead>([&](auto Q) {
+      constexpr int q = decltype(Q)::value;
+      if (jb + q < c) body(jb + q, dt_c[q], d_c[q]);
+    });
+    static_for<kAhead>([&](auto Q) {
+      constexpr int q = decltype(Q)::value;
+      dt_c[q] = dt_n[q];
+      d_c[q] = d_n[q];
+    });
   }
 }
 
@@ -288,26 +353,16 @@ __device__ __forceinline__ void team_eval(Team<MP, NW>& sh, const float* __restr
   for (int m = 0; m < MP; ++m) Rin[m] = cr.S[m] = 0.f;
   cr.A = 1.f;
   cr.D = 0.f;
-  {
-    float dt_n = c > 0 ? dtw[0] : 0.f;
-    int d_n = c > 0 ? (int)dw[0] : kPad;
-    for (int j = 0; j < c; ++j) {
-      const float dt = dt_n;
-      const int d = d_n;
-      if (j + 1 < c) {
-        dt_n = dtw[(int64_t)(j + 1) * T];
-        d_n = dw[(int64_t)(j + 1) * T];
-      }
-      const float a = dt > 0.f ? __expf(-beta * dt) : 1.f;
+  for_steps<T>(dtw, dw, c, [&](int, float dt, int d) {
+    const float a = dt > 0.f ? __expf(-beta * dt) : 1.f;
 #pragma unroll
-      for (int m = 0; m < MP; ++m) {
-        cr.S[m] = a * fmaf(dt, Rin[m], cr.S[m]);
-        Rin[m] = fmaf(a, Rin[m], m == d ? 1.f : 0.f);
-      }
-      cr.A *= a;
-      cr.D += dt;
+    for (int m = 0; m < MP; ++m) {
+      cr.S[m] = a * fmaf(dt, Rin[m], cr.S[m]);
+      Rin[m] = fmaf(a, Rin[m], m == d ? 1.f : 0.f);
     }
-  }
+    cr.A *= a;
+    cr.D += dt;
+  });
   // Pending counts at the chunk's end: the events after its last positive
   // gap (all of them if it has none); R = Rin - P.
   {
@@ -435,66 +490,57 @@ __device__ __forceinline__ void team_eval(Team<MP, NW>& sh, const float* __restr
   f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
   double* gpart = sh.gpart[wv];
   const int gcol = lane & 15, grow0 = (lane >> 4) * 4;  // this lane's G_R[grow0 + r][gcol]
+  constexpr int AS = Team<MP, NW>::AS, VS = Team<MP, NW>::VS, GS = Team<MP, NW>::GS;
   float* vst = sh.vst[wv];
   float* hot = sh.hot[wv];
-  float* gmu = &sh.gmu[wv][lane * Q];
-  {
-    float dt_n = c > 0 ? dtw[0] : 0.f;
-    int d_n = c > 0 ? (int)dw[0] : kPad;
-    for (int j = 0; j < c; ++j) {
-      const float dt = dt_n;
-      const int dr = d_n;
-      if (j + 1 < c) {
-        dt_n = dtw[(int64_t)(j + 1) * T];
-        d_n = dw[(int64_t)(j + 1) * T];
-      }
-      const bool v = dr != kPad;
-      const int d = v ? dr : 0;
-      const bool f = dt > 0.f;
-      const float a = f ? __expf(-beta * dt) : 1.f;
-      const float* arow = &sh.alpha[d * MP];
-      float lam = sh.mu[d], asum = 0.f;
-      float g_old = 0.f;
-      if constexpr (GRAD) g_old = gmu[d];
+  float* gmu = &sh.gmu[wv][lane];
+  for_steps<T>(dtw, dw, c, [&](int j, float dt, int dr) {
+    const bool v = dr != kPad;
+    const int d = v ? dr : 0;
+    const bool f = dt > 0.f;
+    const float a = f ? __expf(-beta * dt) : 1.f;
+    const float* arow = &sh.alpha[d * AS];
+    float lam = sh.mu[d], asum = 0.f;
+    float g_old = 0.f;
+    if constexpr (GRAD) g_old = gmu[d * GS];
 #pragma unroll
-      for (int m = 0; m < MP; ++m) {
-        const float tm = a * Rin[m];
-        S[m] = a * fmaf(dt, Rin[m], S[m]);
-        R[m] = f ? tm : R[m];
-        Rin[m] = tm + (m == dr ? 1.f : 0.f);
-        const float al = arow[m];
-        lam = fmaf(al, R[m], lam);
-        asum = fmaf(al, S[m], asum);
-      }
-      if (v) llp += __logf(lam);
-      if constexpr (GRAD) {
-        // Padding events stage w = 0 (target 0, so their one-hot entry adds 0).
-        const float w = v ? __builtin_amdgcn_rcpf(lam) : 0.f;
-        gbp = fmaf(w, asum, gbp);
-        gmu[d] = g_old + w;  // the lane's own row: no other lane touches it
+    for (int m = 0; m < MP; ++m) {
+      const float tm = a * Rin[m];
+      S[m] = a * fmaf(dt, Rin[m], S[m]);
+      R[m] = f ? tm : R[m];
+      Rin[m] = tm + (m == dr ? 1.f : 0.f);
+      const float al = arow[m];
+      lam = fmaf(al, R[m], lam);
+      asum = fmaf(al, S[m], asum);
+    }
+    if (v) llp += __logf(lam);
+    if constexpr (GRAD) {
+      // Padding events stage w = 0 (target 0, so their one-hot entry adds 0).
+      const float w = v ? __builtin_amdgcn_rcpf(lam) : 0.f;
+      gbp = fmaf(w, asum, gbp);
+      gmu[d * GS] = g_old + w;  // the lane's own entry: no other lane touches it
 #pragma unroll
-        for (int m = 0; m < MP; ++m) vst[m * 64 + lane] = w * R[m];
-        hot[d * 64 + lane] = 1.f;
-        wave_sync();
-        step_outer<MP>(vst, hot, acc0, acc1);
-        wave_sync();
-        hot[d * 64 + lane] = 0.f;
-        if (j % kSpan == kSpan - 1 || j + 1 == c) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r)  // the lane's own entries: no other lane touches them
-            if (grow0 + r < MP && gcol < MP)
-              gpart[(grow0 + r) * MP + gcol] += (double)acc0[r] + (double)acc1[r];
-          acc0 = f32x4{0.f, 0.f, 0.f, 0.f};
-          acc1 = f32x4{0.f, 0.f, 0.f, 0.f};
-        }
-      }
+      for (int m = 0; m < MP; ++m) vst[m * VS + lane] = w * R[m];
+      hot[d * VS + lane] = 1.f;
+      wave_sync();
+      step_outer<MP, VS>(vst, hot, acc0, acc1);
+      wave_sync();
+      hot[d * VS + lane] = 0.f;
       if (j % kSpan == kSpan - 1 || j + 1 == c) {
-        ll64 += (double)llp;
-        gb64 += (double)gbp;
-        llp = gbp = 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)  // the lane's own entries: no other lane touches them
+          if (grow0 + r < MP && gcol < MP)
+            gpart[(grow0 + r) * MP + gcol] += (double)acc0[r] + (double)acc1[r];
+        acc0 = f32x4{0.f, 0.f, 0.f, 0.f};
+        acc1 = f32x4{0.f, 0.f, 0.f, 0.f};
       }
     }
-  }
+    if (j % kSpan == kSpan - 1 || j + 1 == c) {
+      ll64 += (double)llp;
+      gb64 += (double)gbp;
+      llp = gbp = 0.f;
+    }
+  });
   if constexpr (GRAD) {
     // Each wave's Gmu partials (FP64) next to its G_R partials, then the
     // team's sums over waves in order.
@@ -503,7 +549,7 @@ __device__ __forceinline__ void team_eval(Team<MP, NW>& sh, const float* __restr
       const float* gw = sh.gmu[wv];
       double g[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 16
-      for (int l = 0; l < 64; ++l) g[l & 3] += (double)gw[l * Q + lane];
+      for (int l = 0; l < 64; ++l) g[l & 3] += (double)gw[lane * GS + l];
       gpart[MP * MP + lane] = (g[0] + g[1]) + (g[2] + g[3]);
     }
     team_sync<NW>();
@@ -543,7 +589,7 @@ __device__ __forceinline__ void team_colsum(Team<MP, NW>& sh, int M) {
   team_sync<NW>();
   if (t < MP) {
     float s = 0.f;
-    for (int m = 0; m < M; ++m) s += sh.alpha[m * MP + t];
+    for (int m = 0; m < M; ++m) s += sh.alpha[m * Team<MP, NW>::AS + t];
     sh.colsum[t] = s;
   }
   team_sync<NW>();
@@ -557,7 +603,7 @@ __device__ __forceinline__ void team_load(Team<MP, NW>& sh, const float* __restr
   team_sync<NW>();
   for (int e = t; e < MP * MP; e += Team<MP, NW>::T) {
     const int m = e / MP, n = e % MP;
-    sh.alpha[e] = (m < M && n < M) ? alpha[(w * M + m) * M + n] : 0.f;
+    sh.alpha[m * Team<MP, NW>::AS + n] = (m < M && n < M) ? alpha[(w * M + m) * M + n] : 0.f;
   }
   if (t < MP) sh.mu[t] = t < M ? mu[w * M + t] : 0.f;
   if (t == 0) sh.beta = beta[w];
@@ -570,7 +616,7 @@ __device__ __forceinline__ void team_zero(Team<MP, NW>& sh) {
   const int t = team_tid<NW>();
   team_sync<NW>();
   float* g = &sh.gmu[0][0];
-  for (int e = t; e < NW * 64 * Team<MP, NW>::Q; e += Team<MP, NW>::T) g[e] = 0.f;
+  for (int e = t; e < NW * MP * Team<MP, NW>::GS; e += Team<MP, NW>::T) g[e] = 0.f;
   double* gp = &sh.gpart[0][0];
   for (int e = t; e < NW * (MP * MP + MP); e += Team<MP, NW>::T) gp[e] = 0.0;
   team_sync<NW>();
@@ -581,7 +627,7 @@ template <int MP, int NW>
 __device__ __forceinline__ void team_init(Team<MP, NW>& sh) {
   const int t = team_tid<NW>();
   float* h = &sh.hot[0][0];
-  for (int e = t; e < NW * 16 * 64; e += Team<MP, NW>::T) h[e] = 0.f;
+  for (int e = t; e < NW * 16 * Team<MP, NW>::VS; e += Team<MP, NW>::T) h[e] = 0.f;
   team_sync<NW>();
 }
 
@@ -662,7 +708,7 @@ __device__ __forceinline__ void eval_one(Team<MP, NW>& sh, const Events& ev, int
 }
 
 template <int MP, bool GRAD>
-__global__ __launch_bounds__(kBlock) void lpc_eval_kernel(Events ev, int M, const float* mu,
+__global__ __launch_bounds__(kBlock, 2) void lpc_eval_kernel(Events ev, int M, const float* mu,
                                                           const float* alpha, const float* beta,
                                                           double* ll, float* g_mu,
                                                           float* g_alpha, float* g_beta,
@@ -687,6 +733,8 @@ struct Slots {
   static constexpr int OWN = (MP * MP + T - 1) / T;
   static constexpr int K = OWN + 1;
   int M, t, fix_beta;
+  // LDS index of alpha entry e = m * MP + n.
+  __device__ static int at(int e) { return (e / MP) * Team<MP, NW>::AS + e % MP; }
   __device__ int kind(int k) const {
     if (k < OWN) {
       const int e = t + k * T;
@@ -698,14 +746,14 @@ struct Slots {
   }
   __device__ float get(const Team<MP, NW>& sh, int k) const {
     const int kd = kind(k);
-    if (kd == 1) return sh.alpha[t + k * T];
+    if (kd == 1) return sh.alpha[at(t + k * T)];
     if (kd == 2) return sh.mu[t];
     if (kd == 3) return sh.beta;
     return 0.f;
   }
   __device__ void set(Team<MP, NW>& sh, int k, float v) const {
     const int kd = kind(k);
-    if (kd == 1) sh.alpha[t + k * T] = v;
+    if (kd == 1) sh.alpha[at(t + k * T)] = v;
     else if (kd == 2) sh.mu[t] = v;
     else if (kd == 3) sh.beta = v;
   }
@@ -729,14 +777,14 @@ __device__ __forceinline__ void team_store(Team<MP, NW>& sh, int64_t w, int M, f
   const int t = team_tid<NW>();
   team_sync<NW>();
   for (int e = t; e < M * M; e += Team<MP, NW>::T)
-    alpha[w * M * M + e] = sh.alpha[(e / M) * MP + e % M];
+    alpha[w * M * M + e] = sh.alpha[(e / M) * Team<MP, NW>::AS + e % M];
   if (t < M) mu[w * M + t] = sh.mu[t];
   if (t == 0) beta[w] = sh.beta;
 }
 
 // Projected gradient ascent / projected Adam on one window (the rule of the
 // workgroup kernel: evaluate, stop on a non-finite value, on
-// |delta ll| <= ll_tol max(|ll|, 1) or after max_steps updates, else step
+// |delta ll| <= ll_tol max(|ll|, N, 1) or after max_steps updates, else step
 // along the gradient divided by N and project).
 template <int MP, int NW>
 __device__ __forceinline__ void fit_one(Team<MP, NW>& sh, const Events& ev, int64_t w, int M,
@@ -773,7 +821,7 @@ __device__ __forceinline__ void fit_one(Team<MP, NW>& sh, const Events& ev, int6
       st = MDHP_FIT_NONFINITE;
       break;
     }
-    if (s >= 1 && fabs(l - ll_prev) <= o.ll_tol * fmax(fabs(l), 1.0)) {
+    if (s >= 1 && fabs(l - ll_prev) <= o.ll_tol * fmax(fabs(l), (double)max(n, 1))) {
       st = MDHP_FIT_CONVERGED;
       break;
     }
@@ -817,7 +865,7 @@ __device__ __forceinline__ void fit_one(Team<MP, NW>& sh, const Events& ev, int6
 }
 
 template <int MP>
-__global__ __launch_bounds__(kBlock) void lpc_fit_kernel(Events ev, int M, FitParams o,
+__global__ __launch_bounds__(kBlock, 2) void lpc_fit_kernel(Events ev, int M, FitParams o,
                                                          float* mu, float* alpha, float* beta,
                                                          double* ll, int* steps, int* status,
                                                          int* evals_out, int* counter) {
@@ -928,13 +976,19 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
       const double gamma0 = 0.01 / gmax;
       for (int i = 0; i < h; ++i) {
         const int j = (head - 1 - i + kMaxHistory) % kMaxHistory;
+        float sj[K], yj[K];  // both loads in flight together
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          sj[k] = Sv(j, k);
+          yj[k] = Yv(j, k);
+        }
         double v = 0.0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) v += (double)Sv(j, k) * qv[k];
+        for (int k = 0; k < K; ++k) v += (double)sj[k] * qv[k];
         const double a = uni(sh.rho[j]) * team_sum(sh, v);
         if (t == 0) sh.alf[j] = a;
 #pragma unroll
-        for (int k = 0; k < K; ++k) qv[k] -= a * (double)Yv(j, k);
+        for (int k = 0; k < K; ++k) qv[k] -= a * (double)yj[k];
       }
       const double gamma = h > 0 ? sy_new / yy_new : gamma0;
 #pragma unroll
@@ -942,13 +996,19 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
       team_sync<NW>();
       for (int i = h - 1; i >= 0; --i) {
         const int j = (head - 1 - i + kMaxHistory) % kMaxHistory;
+        float sj[K], yj[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          sj[k] = Sv(j, k);
+          yj[k] = Yv(j, k);
+        }
         double v = 0.0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) v += (double)Yv(j, k) * qv[k];
+        for (int k = 0; k < K; ++k) v += (double)yj[k] * qv[k];
         const double bcoef = uni(sh.rho[j]) * team_sum(sh, v);
         const double a = uni(sh.alf[j]);
 #pragma unroll
-        for (int k = 0; k < K; ++k) qv[k] += (a - bcoef) * (double)Sv(j, k);
+        for (int k = 0; k < K; ++k) qv[k] += (a - bcoef) * (double)sj[k];
       }
       double dg = 0.0;
 #pragma unroll
@@ -1033,7 +1093,7 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
       const double l_prev = l;
       l = ln;
       f = fn;
-      if (fabs(l - l_prev) <= o.ll_tol * fmax(fabs(l), 1.0)) {
+      if (fabs(l - l_prev) <= o.ll_tol * fmax(fabs(l), (double)max(n, 1))) {
         st = MDHP_FIT_CONVERGED;
         s += 1;
         break;
@@ -1050,7 +1110,7 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
 }
 
 template <int MP>
-__global__ __launch_bounds__(kBlock) void lpc_lbfgs_kernel(Events ev, int M, FitParams o,
+__global__ __launch_bounds__(kBlock, 2) void lpc_lbfgs_kernel(Events ev, int M, FitParams o,
                                                            float* mu, float* alpha, float* beta,
                                                            double* ll, int* steps, int* status,
                                                            int* evals_out, float* ws,

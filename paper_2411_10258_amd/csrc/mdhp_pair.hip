@@ -363,7 +363,7 @@ __global__ __launch_bounds__(PairCfg<P>::THREADS) void pair_fit_kernel(
         st = MDHP_FIT_NONFINITE;
         break;
       }
-      if (s >= 1 && fabs(l - ll_prev) <= o.ll_tol * fmax(fabs(l), 1.0)) {
+      if (s >= 1 && fabs(l - ll_prev) <= o.ll_tol * fmax(fabs(l), (double)max(n, 1))) {
         st = MDHP_FIT_CONVERGED;
         break;
       }

@@ -406,7 +406,7 @@ __global__ __launch_bounds__(kBlock, kMinBlocks) void shared_fit_kernel(Events e
         st = MDHP_FIT_NONFINITE;
         break;
       }
-      if (s >= 1 && fabs(l - ll_prev) <= o.ll_tol * fmax(fabs(l), 1.0)) {
+      if (s >= 1 && fabs(l - ll_prev) <= o.ll_tol * fmax(fabs(l), (double)max(n, 1))) {
         st = MDHP_FIT_CONVERGED;
         break;
       }
@@ -733,7 +733,7 @@ __global__ __launch_bounds__(kBlock, kMinBlocks) void shared_lbfgs_kernel(Events
         const double l_prev = l;
         l = ln;
         f = fn;
-        if (fabs(l - l_prev) <= o.ll_tol * fmax(fabs(l), 1.0)) {
+        if (fabs(l - l_prev) <= o.ll_tol * fmax(fabs(l), (double)max(n, 1))) {
           st = MDHP_FIT_CONVERGED;
           s += 1;
           break;

@@ -28,18 +28,6 @@ from .surrogate import BINS, Surrogate, TargetStats, features, log_targets, warm
 DEFAULT_FIT = dict(max_steps=1000, optimizer=OPT_LBFGS, ll_tol=1e-7, history=8)
 
 
-def cold_start(b):
-    """mu_m = 0.5 max(N_m, 0.5) / T, beta = 1, alpha = 0.5 beta / M (branching ratio 0.5)."""
-    W, M = b.W, b.M
-    Nm = np.zeros((W, M))
-    wid = np.repeat(np.arange(W), b.counts)
-    np.add.at(Nm, (wid, b.dim), 1.0)
-    mu = (0.5 * np.maximum(Nm, 0.5) / b.T[:, None]).astype(np.float32)
-    beta = np.ones(W, np.float32)
-    alpha = np.full((W, M, M), 0.5 / M, np.float32)
-    return mu, alpha, beta
-
-
 @dataclass
 class DeviceBatch:
     b: object
@@ -65,9 +53,8 @@ def make_batch(M: int, W: int, seed: int, first: int = 0):
 def fit_cold(db: DeviceBatch, opts: FitOptions):
     b = db.b
     plan = Plan(db.offsets, db.t, db.dim, db.T, b.M, BETA_SHARED)
-    mu0, al0, be0 = cold_start(b)
-    out = plan.fit(torch.from_numpy(mu0), torch.from_numpy(al0), torch.from_numpy(be0), opts,
-                   return_evals=True)
+    mu0, al0, be0 = plan.cold_start()
+    out = plan.fit(mu0, al0, be0, opts, return_evals=True)
     plan.close()
     return out
 
@@ -130,7 +117,7 @@ def warm_init(db: DeviceBatch, net: Surrogate, opts: FitOptions, plan: Plan | No
     own = plan is None
     plan = plan or Plan(db.offsets, db.t, db.dim, db.T, b.M, BETA_SHARED)
     x = features(db.offsets, db.t, db.dim, db.T, b.M)
-    mu0, al0, be0 = cold_start(b)
+    mu0, al0, be0 = plan.cold_start()
     mu, al, be, used = warm_start(plan, net, x, net.stats, mu0, al0, be0, opts)
     if own:
         return mu, al, be, used, plan
@@ -142,7 +129,6 @@ def compare(db: DeviceBatch, net: Surrogate, opts: FitOptions | None = None, rep
     iterations and evaluations, and wall-clock per batch (mean of repeats)."""
     opts = opts or FitOptions(**DEFAULT_FIT)
     b = db.b
-    mu0, al0, be0 = (torch.from_numpy(v).to(db.t.device) for v in cold_start(b))
     res = {}
     for label in ("cold", "warm"):
         times = []
@@ -153,7 +139,7 @@ def compare(db: DeviceBatch, net: Surrogate, opts: FitOptions | None = None, rep
             if label == "warm":
                 mu, al, be, used, _ = warm_init(db, net, opts, plan)
             else:
-                mu, al, be, used = mu0, al0, be0, None
+                (mu, al, be), used = plan.cold_start(), None
             out = plan.fit(mu, al, be, opts, return_evals=True)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)

@@ -64,9 +64,11 @@ def test_ties_shared(gpu, oracle_lib, synth_lib, M):
 
 @pytest.mark.parametrize("M,tie_grid", [(5, 0.0), (16, 0.0), (16, 0.5)])
 def test_chunk_boundaries_shared(gpu, oracle_lib, synth_lib, M, tie_grid):
-    # Window sizes at and around multiples of 64 (one chunk per lane), with
-    # and without ties.
-    counts = np.array([0, 1, 2, 63, 64, 65, 127, 128, 129, 640, 641, 4095, 4096, 4097])
+    # Window sizes at and around multiples of 64 (one chunk per lane of a
+    # wavefront), around 1,024 (the size from which a 4-wave workgroup takes a
+    # window, 256 chunks) and a few steps of it, with and without ties.
+    counts = np.array([0, 1, 2, 63, 64, 65, 127, 128, 129, 640, 641, 1023, 1024, 1025, 1279,
+                       4095, 4096, 4097])
     W = len(counts)
     g = np.random.default_rng(40 + M)
     mu = g.uniform(0.2, 1.0, (W, M))
@@ -233,4 +235,22 @@ def test_empty_batch(gpu):
     plan = gpu.Plan(np.zeros(1, np.int64), np.zeros(0), np.zeros(0, np.int32), np.zeros(0), 3)
     ll = plan.loglik(torch.zeros(0, 3), torch.zeros(0, 3, 3), torch.zeros(0))
     assert ll.numel() == 0
+    plan.close()
+
+
+@pytest.mark.parametrize("beta_mode,M", [(0, 7), (0, 16), (0, 40), (1, 5)])
+def test_cold_start_matches_its_definition(gpu, synth_lib, beta_mode, M):
+    """mu_m = 0.5 max(N_m, 0.5) / T (FP64, rounded once), alpha = 0.5 / M, beta = 1."""
+    import torch
+    b = synth_lib.random_small(60 + M, 20, M, beta_mode, n_lo=0, n_hi=300)
+    print(f"[parity] cold start M={M} mode={beta_mode}", flush=True)
+    plan = gpu.Plan(b.offsets, b.t, b.dim, b.T, b.M, beta_mode)
+    mu, al, be = plan.cold_start()
+    torch.cuda.synchronize()
+    Nm = np.stack([np.bincount(b.window(w)[1], minlength=M) for w in range(b.W)])
+    want_mu = (0.5 * np.maximum(Nm, 0.5) / b.T[:, None]).astype(np.float32)
+    assert np.array_equal(mu.cpu().numpy(), want_mu)
+    assert np.all(al.cpu().numpy() == np.float32(0.5 / M))
+    assert np.all(be.cpu().numpy() == 1.0)
+    assert tuple(be.shape) == ((b.W,) if beta_mode == 0 else (b.W, M, M))
     plan.close()
