@@ -16,13 +16,21 @@
 // (suffix sums of the gaps, one exponential per event, LDS atomics into the
 // chunk's state); one group combines the carries in order (the scan of the
 // (a, delta, b_R, b_S) monoid); pass 2 re-runs every chunk from its exact
-// start state in batches of B events and accumulates, per event i with
-// target m = d_i:
+// start state and accumulates, per event i with target m = d_i:
 //   lambda_i = mu_m + sum_n alpha_mn R_n(i)          (Eq. (2) at t_i)
 //   ll      += log lambda_i                          (Part1)
 //   G_R[m][n] += R_n(i) / lambda_i                   (d ll / d alpha, Part1 share)
 //   Gmu[m]  += 1 / lambda_i
 //   Gb      += sum_n alpha_mn S_n(i) / lambda_i      (d ll / d beta, Part1 share)
+// For P >= 32 a group runs its chunk P events at a time: the block's gaps,
+// decays and dimensions are staged in LDS and read back as broadcasts; the
+// recursion runs B = 8 events, then one reduce-scatter across the group's
+// lanes (lane swaps 32 and 16 apart, DPP within rows) turns the B partial
+// dot products alpha_{d_i n} R_n(i) into intensities, P / B lanes per
+// event; the reciprocals return through LDS and G_R[d_i][n] += R_n(i) /
+// lambda_i is one LDS add per event and lane (lane n owns column n, so the
+// adds of one event never collide).  The pending one-hot row [d_i = n] is
+// read from LDS next to alpha_{d_i n}.
 // The compensator (Part2 + Part3, Appendix B) needs
 //   E_n = sum_{k: d_k = n} e^{-beta (T - t_k)},  F_n = sum (T - t_k) e^{-beta (T - t_k)},
 // which are the scan state advanced from the last event to T.
@@ -39,19 +47,33 @@ namespace {
 #endif
 // Events per pass-2 batch (at most the group size).
 constexpr int kBatch = MDHP_BATCH;
+#ifndef MDHP_SCATTER
+#define MDHP_SCATTER 8
+#endif
+// Events per reduce-scatter for groups of 32 or 64 lanes.
+constexpr int kScatter = MDHP_SCATTER;
+
+typedef float f32x32 __attribute__((ext_vector_type(32)));
 
 template <int P>
 struct SharedLds {
+  static constexpr bool kLaneDim = P >= 32;            // pass 2 by reduce-scatter
   static constexpr int G = kBlock / P;                 // groups (chunks) per tile
-  static constexpr int NCOPY = P <= 32 ? kBlock / 64 : 1;  // G_R copies (one per wave if small)
-  float alpha[P * P];  // alpha[m * P + n], zero outside M x M
+  static constexpr int NCOPY = kLaneDim ? 1 : kBlock / 64;  // G_R copies (one per wave if small)
+  static constexpr int AR = kLaneDim ? P + 1 : P;      // rows of ao and gR (row P: padding events)
+  static constexpr int NG = kLaneDim ? G : 1;
+  // .x: alpha[m * P + n], zero outside M x M and in row P; .y: [m == n].
+  float2 ao[AR * P];
   float mu[P];         // zero outside M
   float colsum[P];     // sum_m alpha_mn
   float cR[G][P], cS[G][P], cP[G][P];  // chunk carries, then chunk start states
   float cA[G], cD[G];
   int cF[G];
   float tR[P], tS[P], tP[P];  // state after the last event of the tiles done so far
-  float gR[NCOPY][P * P];     // FP32 tile partials of G_R
+  float gR[NCOPY][AR * P];    // FP32 tile partials of G_R
+  float4 meta[NG][P];         // per group: a, dt, d (bits), mu_d (-1: padding) of a block
+  float wb[NG][16];           // per group: 1 / lambda of a reduce-scatter's events
+  float gmuL[P + 1];          // FP32 Gmu partials (row P: padding)
   double red[4][kBlock];      // end-of-window reductions
   double Cn[P];               // (N_n - E_n) / beta
   double Fn[P];               // F_n
@@ -60,16 +82,70 @@ struct SharedLds {
   float beta;
   int next_window;
   int stop;
+  __device__ float& A(int e) { return ao[e].x; }
 };
+
+// Sums B values (B = 4, 8 or 16) over each group of P lanes (P = 32 or 64)
+// at once: on return every lane holds the group total of value
+// (lane mod P) / (P / B).  Each halving exchange, from the group's top lane
+// bit down, keeps half of the values and adds the partner lane's copy of
+// them: lanes 32 apart (P = 64) and 16 apart by lane swaps, 8 apart by a DPP
+// rotation of the row, then mirrored within 8; plain DPP sums over the lane
+// bits left below end it.
+__device__ __forceinline__ void swap_add32(float& a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a),
+                                                  __builtin_bit_cast(unsigned, b), false, false);
+  const unsigned x = r[0], y = r[1];  // (a bit cast of r[i] itself reads element 0)
+  a = __uint_as_float(x) + __uint_as_float(y);
+}
+__device__ __forceinline__ void swap_add16(float& a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a),
+                                                  __builtin_bit_cast(unsigned, b), false, false);
+  const unsigned x = r[0], y = r[1];  // (a bit cast of r[i] itself reads element 0)
+  a = __uint_as_float(x) + __uint_as_float(y);
+}
+// Keeps v[e + h] where the lane bit is set (else v[e]) and adds the partner's.
+template <int CTRL, int H>
+__device__ __forceinline__ void dpp_halve(float* v, bool bit) {
+#pragma unroll
+  for (int e = 0; e < H; ++e) {
+    const float keep = bit ? v[e + H] : v[e], send = bit ? v[e] : v[e + H];
+    v[e] = keep + dpp<CTRL>(send);
+  }
+}
+template <int P, int B>
+__device__ __forceinline__ float group_reduce_scatter(float (&v)[B]) {
+  static_assert((P == 32 || P == 64) && (B == 4 || B == 8 || B == 16) && B <= P / 4, "");
+  const int lane = threadIdx.x & 63;
+  constexpr int B1 = P == 64 ? B / 2 : B;  // values left after the 32-apart stage
+  if constexpr (P == 64) {
+#pragma unroll
+    for (int e = 0; e < B1; ++e) swap_add32(v[e], v[e + B1]);  // lanes >= 32 keep e + B1
+  }
+  constexpr int B2 = B1 / 2;
+#pragma unroll
+  for (int e = 0; e < B2; ++e) swap_add16(v[e], v[e + B2]);    // odd rows keep e + B2
+  constexpr int B3 = B2 / 2;
+  if constexpr (B3 >= 1) dpp_halve<0x128, B3>(v, lane & 8);    // row_ror:8
+  constexpr int B4 = B3 / 2;
+  if constexpr (B4 >= 1) dpp_halve<0x141, B4>(v, lane & 4);    // row_half_mirror
+  float z = v[0];
+  if constexpr (B3 == 0) z += dpp<0x128>(z);                   // bit 3 left: row_ror:8
+  if constexpr (B4 == 0) z += dpp<0x141>(z);                   // bit 2 left: row_half_mirror
+  z += dpp<0xB1>(z);                                           // quad_perm [1,0,3,2]
+  z += dpp<0x4E>(z);                                           // quad_perm [2,3,0,1]
+  return z;
+}
 
 // Evaluates one window with the parameters already in LDS (alpha, mu,
 // colsum, beta).  Results: sh.scal[0] = ll, and if GRAD: gR64[k] holds
 // G_R[e] for e = tid + k * kBlock (FP64), sh.Cn, sh.Fn, sh.gmu (= d ll/d mu),
-// sh.scal[1] = d ll / d beta.
+// sh.scal[1] = d ll / d beta.  cnt_w: the window's events per dimension.
 template <int P, bool GRAD>
 __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __restrict__ dtg,
                             const uint8_t* __restrict__ dg, int64_t begin, int n, double T,
-                            float end_gap, int M, double (&gR64)[own_count(P)]) {
+                            float end_gap, int M, const int32_t* __restrict__ cnt_w,
+                            double (&gR64)[own_count(P)]) {
   constexpr int G = SharedLds<P>::G;
   constexpr int OWN = own_count(P);
   constexpr int B = kBatch < P ? kBatch : P;
@@ -82,7 +158,9 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
   const uint8_t* __restrict__ dw = dg + begin;
 
   double ll64 = 0.0, gmu64 = 0.0, gb64 = 0.0;
-  int cnt = 0;
+  if constexpr (SharedLds<P>::kLaneDim) {
+    if (tid <= P) sh.gmuL[tid] = 0.f;  // ordered before pass 2 by the barriers below
+  }
   // Group g owns the contiguous chunk [j0, j1) of the window.
   const int c = (n + G - 1) / G;
   const int j0 = min(grp * c, n);
@@ -158,80 +236,194 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
     sh.tP[lane] = Pn;
   }
   __syncthreads();
-  // Pass 2: exact states, intensities and gradient sums, B events per
-  // batch: the recurrence runs over the batch with the gaps, decays and
-  // dims broadcast from the lane that loaded them, the B intensity sums are
-  // independent group reductions, and lane j takes log and reciprocal of
-  // lambda_j for the whole group.
-  {
-    float R = sh.cR[grp][lane], S = sh.cS[grp][lane], Pn = sh.cP[grp][lane];
-    float llp = 0.f, gmup = 0.f, gbp = 0.f;
-    const int nb = (c + B - 1) / B;
-    int jl = lane & (B - 1);
+  // Pass 2: exact states, intensities and gradient sums.  With P = 64 each
+  // wave keeps its chunk's G_R in registers (lane n: column n, rows 0..31 in
+  // gacc0 and 32..63 in gacc1, indexed by the event's uniform target).
+  constexpr bool kRegGR = GRAD && P == 64;
+  f32x32 gacc0, gacc1;
+  if constexpr (SharedLds<P>::kLaneDim) {
+    // P events per block: lane j of the group stages event j (decay, gap,
+    // dimension, mu of its target; padding events have dimension P, whose
+    // alpha and one-hot rows are zero, and mu -1).  Then B events at a time:
+    // the recursion with broadcast reads of the staged values, one
+    // reduce-scatter for their intensities, log and reciprocal there, and
+    // the G_R row adds.
+    constexpr int B = kScatter;
+    constexpr int SH = P == 64 ? (B == 16 ? 2 : B == 8 ? 3 : 4) : (B == 16 ? 1 : B == 8 ? 2 : 3);
+    const int ev_l = lane >> SH;                 // the event whose intensity this lane gets
+    const bool lead = (lane & ((1 << SH) - 1)) == 0;
+    float4* meta = sh.meta[SharedLds<P>::NG > 1 ? grp : 0];
+    float* wb = sh.wb[SharedLds<P>::NG > 1 ? grp : 0];
+    float R = sh.cR[grp][lane], S = sh.cS[grp][lane];
+    float Rin = R + sh.cP[grp][lane];  // R plus the events pending at the current time
+    float llp = 0.f, gbp = 0.f;
+    for (int m = 0; m < 32; ++m) gacc0[m] = gacc1[m] = 0.f;
+    const int nblk = (len + P - 1) / P;
+    int jl = lane;
     float dt_n = jl < len ? dtw[j0 + jl] : 0.f;
-    int d_n = jl < len ? (int)dw[j0 + jl] : 0;
-    for (int bb = 0; bb < nb; ++bb) {
-      const bool vl = jl < len;
+    int d_n = jl < len ? (int)dw[j0 + jl] : P;
+    for (int blk = 0; blk < nblk; ++blk) {
       const float dt_l = dt_n;
-      const float d_l = __builtin_bit_cast(float, d_n);
-      const int nvalid = min(B, len - bb * B);  // valid events of this batch (may be <= 0)
-      jl += B;
-      if (bb + 1 < nb) {  // prefetch the next batch
+      const int d_l = d_n;
+      jl += P;
+      if (blk + 1 < nblk) {  // prefetch the next block
         dt_n = jl < len ? dtw[j0 + jl] : 0.f;
-        d_n = jl < len ? (int)dw[j0 + jl] : 0;
+        d_n = jl < len ? (int)dw[j0 + jl] : P;
       }
-      const float a_l = __expf(-beta * dt_l);
-      float Rj[B], ASj[B], Lj[B];  // R(j), alpha_{d_j n} S_n(j), alpha_{d_j n} R_n(j)
-      int Dj[B];
-      static_for<B>([&](auto J) {
-        constexpr int j = decltype(J)::value;
-        const float dt = group_bcast<P, j>(dt_l);
-        const float a = group_bcast<P, j>(a_l);
-        const int d = __builtin_bit_cast(int, group_bcast<P, j>(d_l));
-        const bool f = dt > 0.f;
-        const float X = f ? R + Pn : R;
-        R = a * X;
-        S = fmaf(a, S, dt * R);
-        Pn = f ? 0.f : Pn;
-        const float al = sh.alpha[d * P + lane];
-        Rj[j] = R;
-        ASj[j] = al * S;
-        Dj[j] = d;
-        Lj[j] = al * R;
-        const bool mine = j < nvalid && d == lane;
-        Pn += mine ? 1.f : 0.f;
-        cnt += mine ? 1 : 0;
-      });
-      static_for<B>([&](auto J) {
-        constexpr int j = decltype(J)::value;
-        Lj[j] = group_sum<P>(Lj[j]);
-      });
-      float lk = Lj[0];
-      static_for<B>([&](auto J) {
-        constexpr int j = decltype(J)::value;
-        if (j > 0) lk = (lane & (B - 1)) == j ? Lj[j] : lk;
-      });
-      lk += sh.mu[__builtin_bit_cast(int, d_l)];
-      const float lg = __logf(lk);
-      llp += (vl && lane < B) ? lg : 0.f;
-      if constexpr (GRAD) {
-        const float wk = vl ? __builtin_amdgcn_rcpf(lk) : 0.f;
+      wave_sync();  // the previous block's reads are done
+      meta[lane] = make_float4(__expf(-beta * dt_l), dt_l, __builtin_bit_cast(float, d_l),
+                               d_l < P ? sh.mu[d_l] : -1.f);
+      wave_sync();
+#pragma unroll 1
+      for (int sb = 0; sb < P; sb += B) {
+        float L[B], AS[B], Rj[B];
+        int Dj[B];
         static_for<B>([&](auto J) {
           constexpr int j = decltype(J)::value;
-          const float w = group_bcast<P, j>(wk);  // zero for events past the chunk end
-          atomicAdd(&gRc[Dj[j] * P + lane], w * Rj[j]);
-          gbp = fmaf(w, ASj[j], gbp);
-          gmup += Dj[j] == lane ? w : 0.f;
+          const float4 m = meta[sb + j];
+          const float a = m.x, dt = m.y;
+          const int d = __builtin_bit_cast(int, m.z);
+          const float x = a * Rin;  // decayed over the gap; R moves only when time does
+          S = fmaf(a, S, dt * x);
+          R = dt > 0.f ? x : R;
+          const float2 ao = sh.ao[d * P + lane];
+          L[j] = ao.x * R;
+          AS[j] = ao.x * S;
+          Rj[j] = R;
+          Dj[j] = d;
+          Rin = x + ao.y;  // the event itself is pending until time moves on
         });
+        float lam = group_reduce_scatter<P, B>(L);
+        const float4 me = meta[sb + ev_l];
+        const bool valid = me.w >= 0.f;
+        lam += me.w;
+        llp += (lead && valid) ? __logf(lam) : 0.f;
+        if constexpr (GRAD) {
+          const float w = valid ? __builtin_amdgcn_rcpf(lam) : 0.f;
+          if (lead) {
+            wb[ev_l] = w;
+            if (valid) atomicAdd(&sh.gmuL[__builtin_bit_cast(int, me.z)], w);
+          }
+          wave_sync();
+          float wv[B];
+#pragma unroll
+          for (int q = 0; q < B / 4; ++q) {
+            const float4 w4 = reinterpret_cast<const float4*>(wb)[q];
+            wv[4 * q] = w4.x;
+            wv[4 * q + 1] = w4.y;
+            wv[4 * q + 2] = w4.z;
+            wv[4 * q + 3] = w4.w;
+          }
+#pragma unroll
+          for (int j = 0; j < B; ++j) {
+            const float x = wv[j] * Rj[j];
+            if constexpr (kRegGR) {
+              // Row d of the wave's G_R registers (d is uniform: one event).
+              const int d = __builtin_amdgcn_readfirstlane(Dj[j]);
+              const int dl = d & 31;
+              const bool hi = d >= 32;
+              gacc0[dl] += hi ? 0.f : x;
+              gacc1[dl] += hi ? x : 0.f;
+            } else {
+              atomicAdd(&sh.gR[0][Dj[j] * P + lane], x);
+            }
+            gbp = fmaf(wv[j], AS[j], gbp);
+          }
+          wave_sync();  // wb is rewritten by the next events
+        }
       }
     }
     ll64 += (double)llp;
-    gmu64 += (double)gmup;
     gb64 += (double)gbp;
+  } else {
+    // B events per batch: the recurrence runs over the batch with the gaps,
+    // decays and dims broadcast from the lane that loaded them, the B intensity sums are
+    // independent group reductions, and lane j takes log and reciprocal of
+    // lambda_j for the whole group.
+    {
+      float R = sh.cR[grp][lane], S = sh.cS[grp][lane], Pn = sh.cP[grp][lane];
+      float llp = 0.f, gmup = 0.f, gbp = 0.f;
+      const int nb = (c + B - 1) / B;
+      int jl = lane & (B - 1);
+      float dt_n = jl < len ? dtw[j0 + jl] : 0.f;
+      int d_n = jl < len ? (int)dw[j0 + jl] : 0;
+      for (int bb = 0; bb < nb; ++bb) {
+        const bool vl = jl < len;
+        const float dt_l = dt_n;
+        const float d_l = __builtin_bit_cast(float, d_n);
+        const int nvalid = min(B, len - bb * B);  // valid events of this batch (may be <= 0)
+        jl += B;
+        if (bb + 1 < nb) {  // prefetch the next batch
+          dt_n = jl < len ? dtw[j0 + jl] : 0.f;
+          d_n = jl < len ? (int)dw[j0 + jl] : 0;
+        }
+        const float a_l = __expf(-beta * dt_l);
+        float Rj[B], ASj[B], Lj[B];  // R(j), alpha_{d_j n} S_n(j), alpha_{d_j n} R_n(j)
+        int Dj[B];
+        static_for<B>([&](auto J) {
+          constexpr int j = decltype(J)::value;
+          const float dt = group_bcast<P, j>(dt_l);
+          const float a = group_bcast<P, j>(a_l);
+          const int d = __builtin_bit_cast(int, group_bcast<P, j>(d_l));
+          const bool f = dt > 0.f;
+          const float X = f ? R + Pn : R;
+          R = a * X;
+          S = fmaf(a, S, dt * R);
+          Pn = f ? 0.f : Pn;
+          const float al = sh.A(d * P + lane);
+          Rj[j] = R;
+          ASj[j] = al * S;
+          Dj[j] = d;
+          Lj[j] = al * R;
+          Pn += (j < nvalid && d == lane) ? 1.f : 0.f;
+        });
+        static_for<B>([&](auto J) {
+          constexpr int j = decltype(J)::value;
+          Lj[j] = group_sum<P>(Lj[j]);
+        });
+        float lk = Lj[0];
+        static_for<B>([&](auto J) {
+          constexpr int j = decltype(J)::value;
+          if (j > 0) lk = (lane & (B - 1)) == j ? Lj[j] : lk;
+        });
+        lk += sh.mu[__builtin_bit_cast(int, d_l)];
+        const float lg = __logf(lk);
+        llp += (vl && lane < B) ? lg : 0.f;
+        if constexpr (GRAD) {
+          const float wk = vl ? __builtin_amdgcn_rcpf(lk) : 0.f;
+          static_for<B>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            const float w = group_bcast<P, j>(wk);  // zero for events past the chunk end
+            atomicAdd(&gRc[Dj[j] * P + lane], w * Rj[j]);
+            gbp = fmaf(w, ASj[j], gbp);
+            gmup += Dj[j] == lane ? w : 0.f;
+          });
+        }
+      }
+      ll64 += (double)llp;
+      gmu64 += (double)gmup;
+      gb64 += (double)gbp;
+    }
   }
 #pragma unroll
   for (int k = 0; k < OWN; ++k) gR64[k] = 0.0;
-  if constexpr (GRAD) {
+  if constexpr (kRegGR) {
+    // The waves' register G_R, one wave at a time through LDS.
+#pragma unroll 1
+    for (int r = 0; r < kBlock / 64; ++r) {
+      __syncthreads();
+      if ((tid >> 6) == r) {
+#pragma unroll
+        for (int m = 0; m < 32; ++m) {
+          sh.gR[0][m * P + lane] = gacc0[m];
+          sh.gR[0][(m + 32) * P + lane] = gacc1[m];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < OWN; ++k) gR64[k] += (double)sh.gR[0][tid + k * kBlock];
+    }
+  } else if constexpr (GRAD) {
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < OWN; ++k) {
@@ -248,49 +440,49 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
     }
   }
 
-  // End of window: reduce the per-lane partials over groups.
+  // End of window: reduce the per-lane partials over groups (lane n of
+  // wave 0 takes component n), then the window sums over the wave.
   __syncthreads();
   sh.red[0][tid] = ll64;
   sh.red[1][tid] = gmu64;
   sh.red[2][tid] = gb64;
-  sh.red[3][tid] = (double)cnt;
   __syncthreads();
-  if (tid < P) {
-    double l = 0.0, gm = 0.0, gb = 0.0, nn = 0.0;
-    for (int g = 0; g < G; ++g) {
-      l += sh.red[0][g * P + tid];
-      gm += sh.red[1][g * P + tid];
-      gb += sh.red[2][g * P + tid];
-      nn += sh.red[3][g * P + tid];
-    }
-    // Advance the end state to T: E_n and F_n of the compensator.
-    const double gap = (double)end_gap;
-    const double b = (double)beta;
-    const double a = exp(-b * gap);
-    const double E = a * ((double)sh.tR[tid] + (double)sh.tP[tid]);
-    const double F = a * (double)sh.tS[tid] + gap * E;
-    const double C = (nn - E) / b;
-    const bool in = tid < M;
-    sh.Cn[tid] = in ? C : 0.0;
-    sh.Fn[tid] = in ? F : 0.0;
-    sh.gmu[tid] = in ? gm - T : 0.0;
-    // Per-lane pieces of the window sums, reduced below.
-    sh.red[0][tid] = l;                                                     // Part1
-    sh.red[1][tid] = in ? (double)sh.mu[tid] : 0.0;                         // sum mu
-    sh.red[2][tid] = in ? (double)sh.colsum[tid] * C : 0.0;                 // Part3 (sign below)
-    sh.red[3][tid] = in ? gb + (double)sh.colsum[tid] * (F - C) / b : 0.0;  // -d ll / d beta
-  }
-  __syncthreads();
-  if (tid == 0) {
+  if (tid < 64) {
     double p1 = 0.0, smu = 0.0, p3 = 0.0, gbeta = 0.0;
-    for (int k = 0; k < P; ++k) {
-      p1 += sh.red[0][k];
-      smu += sh.red[1][k];
-      p3 += sh.red[2][k];
-      gbeta += sh.red[3][k];
+    if (tid < P) {
+      double l = 0.0, gm = 0.0, gb = 0.0;
+#pragma unroll 1
+      for (int g = 0; g < G; ++g) {
+        l += sh.red[0][g * P + tid];
+        gm += sh.red[1][g * P + tid];
+        gb += sh.red[2][g * P + tid];
+      }
+      if constexpr (SharedLds<P>::kLaneDim) gm = (double)sh.gmuL[tid];
+      const bool in = tid < M;
+      const double nn = in ? (double)cnt_w[tid] : 0.0;
+      // Advance the end state to T: E_n and F_n of the compensator.
+      const double gap = (double)end_gap;
+      const double b = (double)beta;
+      const double a = exp(-b * gap);
+      const double E = a * ((double)sh.tR[tid] + (double)sh.tP[tid]);
+      const double F = a * (double)sh.tS[tid] + gap * E;
+      const double C = (nn - E) / b;
+      sh.Cn[tid] = in ? C : 0.0;
+      sh.Fn[tid] = in ? F : 0.0;
+      sh.gmu[tid] = in ? gm - T : 0.0;
+      p1 = l;                                                     // Part1
+      smu = in ? (double)sh.mu[tid] : 0.0;                        // sum mu
+      p3 = in ? (double)sh.colsum[tid] * C : 0.0;                 // Part3 (sign below)
+      gbeta = in ? gb + (double)sh.colsum[tid] * (F - C) / b : 0.0;  // -d ll / d beta
     }
-    sh.scal[0] = p1 - T * smu - p3;
-    sh.scal[1] = -gbeta;
+    p1 = wave_sum(p1);
+    smu = wave_sum(smu);
+    p3 = wave_sum(p3);
+    gbeta = wave_sum(gbeta);
+    if (tid == 0) {
+      sh.scal[0] = p1 - T * smu - p3;
+      sh.scal[1] = -gbeta;
+    }
   }
   __syncthreads();
 }
@@ -302,24 +494,30 @@ __device__ void load_params(SharedLds<P>& sh, const float* __restrict__ mu,
   const int tid = threadIdx.x;
   for (int e = tid; e < P * P; e += kBlock) {
     const int m = e / P, n = e % P;
-    sh.alpha[e] = (m < M && n < M) ? alpha[(w * M + m) * M + n] : 0.f;
+    sh.A(e) = (m < M && n < M) ? alpha[(w * M + m) * M + n] : 0.f;
   }
   if (tid < P) sh.mu[tid] = tid < M ? mu[w * M + tid] : 0.f;
   if (tid == 0) sh.beta = beta[w];
   __syncthreads();
   if (tid < P) {
     float s = 0.f;
-    for (int m = 0; m < M; ++m) s += sh.alpha[m * P + tid];
+    for (int m = 0; m < M; ++m) s += sh.A(m * P + tid);
     sh.colsum[tid] = s;
   }
   __syncthreads();
 }
 
-// LDS is not initialised at launch; the G_R tile accumulators must start at
-// zero (eval_window leaves them zero after every tile).
+// LDS is not initialised at launch: the G_R tile accumulators must start at
+// zero (eval_window leaves them zero after every tile), the one-hot column
+// of ao is the identity and ao's padding row P is zero.
 template <int P>
-__device__ void zero_accumulators(SharedLds<P>& sh) {
-  for (int e = threadIdx.x; e < SharedLds<P>::NCOPY * P * P; e += kBlock) (&sh.gR[0][0])[e] = 0.f;
+__device__ void init_lds(SharedLds<P>& sh) {
+  constexpr int AR = SharedLds<P>::AR;
+  for (int e = threadIdx.x; e < SharedLds<P>::NCOPY * AR * P; e += kBlock) (&sh.gR[0][0])[e] = 0.f;
+  for (int e = threadIdx.x; e < AR * P; e += kBlock) {
+    const int m = e / P, n = e % P;
+    sh.ao[e] = make_float2(0.f, m == n ? 1.f : 0.f);
+  }
 }
 
 template <int P>
@@ -331,7 +529,7 @@ __device__ int next_window(SharedLds<P>& sh, int* counter, int first) {
 }
 
 template <int P, bool GRAD>
-__global__ __launch_bounds__(kBlock, kMinBlocks) void shared_eval_kernel(Events ev, int M, const float* mu,
+__global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_eval_kernel(Events ev, int M, const float* mu,
                                                              const float* alpha,
                                                              const float* beta, double* ll,
                                                              float* g_mu, float* g_alpha,
@@ -340,12 +538,12 @@ __global__ __launch_bounds__(kBlock, kMinBlocks) void shared_eval_kernel(Events 
   constexpr int OWN = own_count(P);
   double gR64[OWN];
   const int tid = threadIdx.x;
-  if constexpr (GRAD) zero_accumulators(sh);
+  init_lds(sh);
   for (int q = next_window(sh, counter, 1); q < ev.W; q = next_window(sh, counter, 0)) {
     const int64_t w = ev.order[q];
     load_params(sh, mu, alpha, beta, w, M);
     const double T = ev.T[w];
-    eval_window<P, GRAD>(sh, ev.dt, ev.d, ev.begin[w], ev.n[w], T, ev.end_gap[w], M, gR64);
+    eval_window<P, GRAD>(sh, ev.dt, ev.d, ev.begin[w], ev.n[w], T, ev.end_gap[w], M, ev.counts + w * M, gR64);
     if (tid == 0) ll[w] = sh.scal[0];
     if constexpr (GRAD) {
       if (tid == 0) g_beta[w] = (float)sh.scal[1];
@@ -363,7 +561,7 @@ __global__ __launch_bounds__(kBlock, kMinBlocks) void shared_eval_kernel(Events 
 
 // Persistent projected-gradient fit (see mdhp_fit_opts for the rule).
 template <int P>
-__global__ __launch_bounds__(kBlock, kMinBlocks) void shared_fit_kernel(Events ev, int M, FitParams o,
+__global__ __launch_bounds__(kBlock, (P == 32 ? 2 : kMinBlocks)) void shared_fit_kernel(Events ev, int M, FitParams o,
                                                             float* mu, float* alpha, float* beta,
                                                             double* ll, int* steps, int* status,
                                                             int* evals_out, int* counter) {
@@ -372,7 +570,7 @@ __global__ __launch_bounds__(kBlock, kMinBlocks) void shared_fit_kernel(Events e
   double gR64[OWN];
   float m1a[OWN], m2a[OWN];
   const int tid = threadIdx.x;
-  zero_accumulators(sh);
+  init_lds(sh);
   for (int q = next_window(sh, counter, 1); q < ev.W; q = next_window(sh, counter, 0)) {
     const int64_t w = ev.order[q];
     load_params(sh, mu, alpha, beta, w, M);
@@ -388,7 +586,7 @@ __global__ __launch_bounds__(kBlock, kMinBlocks) void shared_fit_kernel(Events e
     double ll_prev = 0.0, b1t = 1.0, b2t = 1.0;
     int s = 0, st = MDHP_FIT_MAX_STEPS;
     for (s = 0;; ++s) {
-      eval_window<P, true>(sh, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], M, gR64);
+      eval_window<P, true>(sh, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], M, ev.counts + w * M, gR64);
       const double l = sh.scal[0];
       // Finiteness of ll and of the whole gradient (one flag per block).
       if (tid == 0) sh.stop = isfinite(l) && isfinite(sh.scal[1]) ? 0 : 1;
@@ -433,8 +631,8 @@ __global__ __launch_bounds__(kBlock, kMinBlocks) void shared_fit_kernel(Events e
         const int m = e / P, nn = e % P;
         if (e < P * P && m < M && nn < M) {
           const double g = gR64[k] - sh.Cn[nn];
-          const double v = (double)sh.alpha[e] + step(g, m1a[k], m2a[k]);
-          sh.alpha[e] = (float)fmax(v, 0.0);
+          const double v = (double)sh.A(e) + step(g, m1a[k], m2a[k]);
+          sh.A(e) = (float)fmax(v, 0.0);
         }
       }
       if (tid < M) {
@@ -448,13 +646,13 @@ __global__ __launch_bounds__(kBlock, kMinBlocks) void shared_fit_kernel(Events e
       __syncthreads();
       if (tid < P) {
         float cs = 0.f;
-        for (int m = 0; m < M; ++m) cs += sh.alpha[m * P + tid];
+        for (int m = 0; m < M; ++m) cs += sh.A(m * P + tid);
         sh.colsum[tid] = cs;
       }
       __syncthreads();
     }
     // theta_s of the last evaluation is in LDS.
-    for (int e = tid; e < M * M; e += kBlock) alpha[w * M * M + e] = sh.alpha[(e / M) * P + e % M];
+    for (int e = tid; e < M * M; e += kBlock) alpha[w * M * M + e] = sh.A((e / M) * P + e % M);
     if (tid < M) mu[w * M + tid] = sh.mu[tid];
     if (tid == 0) {
       beta[w] = sh.beta;
@@ -503,7 +701,7 @@ __device__ __forceinline__ double block_max_abs(double v, double* scratch) {
 // reads and writes; the scalars of the two-loop recursion come from block
 // reductions.
 template <int P>
-__global__ __launch_bounds__(kBlock, kMinBlocks) void shared_lbfgs_kernel(Events ev, int M, FitParams o,
+__global__ __launch_bounds__(kBlock, (P == 32 ? 2 : kMinBlocks)) void shared_lbfgs_kernel(Events ev, int M, FitParams o,
                                                               float* mu, float* alpha,
                                                               float* beta, double* ll,
                                                               int* steps, int* status,
@@ -528,7 +726,7 @@ __global__ __launch_bounds__(kBlock, kMinBlocks) void shared_lbfgs_kernel(Events
   auto Yv = [&](int j, int k) -> float& {
     return base[((4 + kMaxHistory + j) * K + k) * kBlock + tid];
   };
-  zero_accumulators(sh);
+  init_lds(sh);
   for (int q = next_window(sh, counter, 1); q < ev.W; q = next_window(sh, counter, 0)) {
     const int64_t w = ev.order[q];
     load_params(sh, mu, alpha, beta, w, M);
@@ -554,14 +752,14 @@ __global__ __launch_bounds__(kBlock, kMinBlocks) void shared_lbfgs_kernel(Events
     };
     auto get_param = [&](int k) -> float {
       const int kd = kind(k);
-      if (kd == 1) return sh.alpha[tid + k * kBlock];
+      if (kd == 1) return sh.A(tid + k * kBlock);
       if (kd == 2) return sh.mu[tid];
       if (kd == 3) return sh.beta;
       return 0.f;
     };
     auto set_param = [&](int k, float v) {
       const int kd = kind(k);
-      if (kd == 1) sh.alpha[tid + k * kBlock] = v;
+      if (kd == 1) sh.A(tid + k * kBlock) = v;
       else if (kd == 2) sh.mu[tid] = v;
       else if (kd == 3) sh.beta = v;
     };
@@ -577,14 +775,14 @@ __global__ __launch_bounds__(kBlock, kMinBlocks) void shared_lbfgs_kernel(Events
       __syncthreads();
       if (tid < P) {
         float cs = 0.f;
-        for (int m = 0; m < M; ++m) cs += sh.alpha[m * P + tid];
+        for (int m = 0; m < M; ++m) cs += sh.A(m * P + tid);
         sh.colsum[tid] = cs;
       }
       __syncthreads();
     };
     // Evaluates at the LDS parameters; true if ll and the gradient are finite.
     auto evaluate = [&]() -> bool {
-      eval_window<P, true>(sh, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], M, gR64);
+      eval_window<P, true>(sh, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], M, ev.counts + w * M, gR64);
       if (tid == 0) flag = isfinite(sh.scal[0]) && isfinite(sh.scal[1]) ? 0 : 1;
       __syncthreads();
       bool bad = false;
@@ -741,7 +939,7 @@ __global__ __launch_bounds__(kBlock, kMinBlocks) void shared_lbfgs_kernel(Events
       }
     }
     __syncthreads();
-    for (int e = tid; e < M * M; e += kBlock) alpha[w * M * M + e] = sh.alpha[(e / M) * P + e % M];
+    for (int e = tid; e < M * M; e += kBlock) alpha[w * M * M + e] = sh.A((e / M) * P + e % M);
     if (tid < M) mu[w * M + tid] = sh.mu[tid];
     if (tid == 0) {
       beta[w] = sh.beta;

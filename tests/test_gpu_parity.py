@@ -84,6 +84,30 @@ def test_chunk_boundaries_shared(gpu, oracle_lib, synth_lib, M, tie_grid):
     _check_grad(gpu, oracle_lib, b, *th, f"chunk boundaries M={M} grid={tie_grid}")
 
 
+@pytest.mark.parametrize("M,tie_grid", [(20, 0.0), (33, 0.5), (64, 0.0), (64, 0.25)])
+def test_chunk_boundaries_wide(gpu, oracle_lib, synth_lib, M, tie_grid):
+    # M > 16: one workgroup per window, 256 / P chunks of P-event blocks, B = 8
+    # events per reduce-scatter.  Sizes at and around multiples of the block,
+    # the chunk and the sub-batch, with and without ties.
+    counts = np.array([0, 1, 2, 3, 7, 8, 9, 31, 32, 33, 63, 64, 65, 127, 128, 129, 255, 256,
+                       257, 511, 512, 513, 1023, 1024, 1025, 2047, 2049, 4100])
+    W = len(counts)
+    g = np.random.default_rng(70 + M)
+    mu = g.uniform(0.2, 1.0, (W, M))
+    alpha = g.uniform(0.0, 0.5 / M, (W, M, M))
+    beta = g.uniform(0.5, 2.5, W)
+    off, t, d, T = synth_lib.simulate(M, 0, mu, alpha, beta, counts=counts, seed=70 + M,
+                                      nthreads=1)
+    if tie_grid > 0:
+        t = np.floor(t / tie_grid) * tie_grid
+        T = np.maximum(T, tie_grid)
+    b = synth_lib.Batch(M, 0, off, t, d, T, mu, alpha, beta)
+    if tie_grid > 0:
+        assert np.sum(np.diff(b.t) == 0) > 100
+    th = _random_theta(b, M)
+    _check_grad(gpu, oracle_lib, b, *th, f"wide chunk boundaries M={M} grid={tie_grid}")
+
+
 def test_all_events_tied(gpu, oracle_lib, synth_lib):
     # One window whose 3,000 events all share one time, one with an event at T.
     M = 3
