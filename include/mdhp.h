@@ -195,6 +195,51 @@ mdhp_status mdhp_check_params(mdhp_plan* plan, const float* mu, const float* alp
                               const float* beta, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Schedule autotuning.  A plan runs with one of a few schedules, chosen per
+ * plan because the best one depends on its window sizes:
+ *   kind 1 (one decay per window, M <= 16): the number of events from which
+ *     a window is run by a whole workgroup of 256 lanes instead of one
+ *     wavefront of 64 (512, 1024, 2048, 4096 or MDHP_TEAM_NEVER; the events'
+ *     layout in the plan depends on it; default 1024);
+ *   kind 2 (one decay per window, 16 < M <= 64): the events per
+ *     reduce-scatter of the intensity sums (4, 8 or 16 for M > 32; 4 or 8
+ *     for M <= 32; default 8);
+ *   kind 0 (per-pair decays): nothing to choose.
+ * The schedule changes the order of floating-point sums, never the result
+ * beyond rounding. */
+#define MDHP_TUNE_MAX 8
+#define MDHP_TEAM_NEVER 2147483647
+
+typedef struct mdhp_tune_result {
+  int32_t kind;                 /* 0, 1 or 2 as above */
+  int32_t n;                    /* candidates timed */
+  int32_t chosen;               /* index of the kept candidate */
+  int32_t value[MDHP_TUNE_MAX]; /* candidate schedules */
+  float ms[MDHP_TUNE_MAX];      /* mean milliseconds per repetition */
+} mdhp_tune_result;
+
+/* Times every candidate schedule of the plan on its own windows from the
+ * cold start (mdhp_cold_start) and keeps the fastest.  opts == NULL times
+ * `reps` evaluations of mdhp_grad; otherwise `reps` calls of mdhp_fit_batch
+ * with opts (each after one untimed warm-up).  `batch` must be the batch the
+ * plan was created from (kind 1 re-prepares it per candidate; unused for
+ * kinds 0 and 2, may be NULL there).  Synchronous on `stream`; allocates and
+ * frees device scratch memory (parameter and output copies), so it must not
+ * be called during stream capture.  On error the plan keeps a valid
+ * schedule.  Results in *result. */
+mdhp_status mdhp_plan_autotune(mdhp_plan* plan, const mdhp_batch* batch, const mdhp_fit_opts* opts,
+                               int32_t reps, mdhp_tune_result* result, void* stream);
+
+/* Sets the plan's schedule to `value` (a candidate of its kind, else
+ * MDHP_E_INVAL) without timing; `batch` as for mdhp_plan_autotune.
+ * Synchronous on `stream` when the events are re-prepared. */
+mdhp_status mdhp_plan_set_schedule(mdhp_plan* plan, const mdhp_batch* batch, int32_t value,
+                                   void* stream);
+
+/* The plan's current schedule value (0 for kind 0 or a NULL plan). */
+int32_t mdhp_plan_schedule(const mdhp_plan* plan);
+
+/* ------------------------------------------------------------------------
  * Learned warm start (an addition around the paper's solver, which fits
  * every window from scratch): count-histogram features, a 3-layer ReLU MLP
  * trained on the GPU with BF16 MFMA GEMMs (FP32 accumulation and master

@@ -22,7 +22,8 @@ EXPORTS = (
     "mdhp_surrogate_destroy", "mdhp_surrogate_num_params", "mdhp_surrogate_get_weights",
     "mdhp_surrogate_set_weights", "mdhp_surrogate_forward", "mdhp_surrogate_get_hidden",
     "mdhp_surrogate_backward", "mdhp_surrogate_get_gradients", "mdhp_surrogate_adam",
-    "mdhp_surrogate_train_step", "mdhp_warm_start", "mdhp_cold_start",
+    "mdhp_surrogate_train_step", "mdhp_warm_start", "mdhp_cold_start", "mdhp_plan_autotune",
+    "mdhp_plan_set_schedule", "mdhp_plan_schedule",
 )
 
 MDHP_OK = 0
@@ -32,6 +33,8 @@ BETA_SHARED, BETA_PAIR = 0, 1
 OPT_PGD, OPT_PADAM, OPT_LBFGS = 0, 1, 2
 FIT_CONVERGED, FIT_MAX_STEPS, FIT_NONFINITE, FIT_STALLED = 0, 1, 2, 3
 MAX_M = 64
+TUNE_MAX = 8
+TEAM_NEVER = 2147483647
 
 
 class MdhpBatch(ctypes.Structure):
@@ -47,6 +50,11 @@ class MdhpFitOpts(ctypes.Structure):
                 ("mu_floor_rel", ctypes.c_double), ("beta_floor_rel", ctypes.c_double),
                 ("adam_b1", ctypes.c_double), ("adam_b2", ctypes.c_double),
                 ("adam_eps", ctypes.c_double)]
+
+
+class MdhpTuneResult(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32), ("chosen", ctypes.c_int32),
+                ("value", ctypes.c_int32 * TUNE_MAX), ("ms", ctypes.c_float * TUNE_MAX)]
 
 
 class MdhpError(RuntimeError):
@@ -81,6 +89,11 @@ def load() -> ctypes.CDLL:
     lib.mdhp_fit_batch.argtypes = [P, ctypes.POINTER(MdhpFitOpts), P, P, P, P, P, P, P, P]
     lib.mdhp_check_params.argtypes = [P, P, P, P, P]
     lib.mdhp_cold_start.argtypes = [P, P, P, P, P]
+    lib.mdhp_plan_autotune.argtypes = [P, ctypes.POINTER(MdhpBatch), ctypes.POINTER(MdhpFitOpts),
+                                       I32, ctypes.POINTER(MdhpTuneResult), P]
+    lib.mdhp_plan_set_schedule.argtypes = [P, ctypes.POINTER(MdhpBatch), I32, P]
+    lib.mdhp_plan_schedule.argtypes = [P]
+    lib.mdhp_plan_schedule.restype = I32
     lib.mdhp_features.argtypes = [ctypes.POINTER(MdhpBatch), I32, I32, P, P]
     lib.mdhp_surrogate_create.argtypes = [I32, I32, I32, I32, ctypes.c_uint64, ctypes.POINTER(P)]
     lib.mdhp_surrogate_destroy.argtypes = [P]
@@ -106,7 +119,8 @@ def load() -> ctypes.CDLL:
                  "mdhp_surrogate_get_weights", "mdhp_surrogate_set_weights",
                  "mdhp_surrogate_get_gradients", "mdhp_surrogate_forward",
                  "mdhp_surrogate_get_hidden", "mdhp_surrogate_backward", "mdhp_surrogate_adam",
-                 "mdhp_surrogate_train_step", "mdhp_warm_start"):
+                 "mdhp_surrogate_train_step", "mdhp_warm_start", "mdhp_cold_start",
+                 "mdhp_plan_autotune", "mdhp_plan_set_schedule"):
         getattr(lib, name).restype = I32
     _lib = lib
     return lib

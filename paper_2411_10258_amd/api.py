@@ -18,6 +18,7 @@ from ._lib import (BETA_PAIR, BETA_SHARED, FIT_CONVERGED, FIT_MAX_STEPS, FIT_NON
 
 __all__ = ["Plan", "FitOptions", "mdhp_plan_create", "mdhp_plan_destroy", "mdhp_loglik",
            "mdhp_grad", "mdhp_fit_batch", "mdhp_check_params", "mdhp_cold_start", "mdhp_status_string",
+           "mdhp_plan_autotune", "mdhp_plan_set_schedule", "mdhp_plan_schedule",
            "BETA_SHARED", "BETA_PAIR", "OPT_PGD", "OPT_PADAM", "OPT_LBFGS", "FIT_CONVERGED",
            "FIT_MAX_STEPS", "FIT_NONFINITE", "FIT_STALLED", "MdhpError"]
 
@@ -65,16 +66,22 @@ def mdhp_status_string(status: int) -> str:
     return _lib.load().mdhp_status_string(int(status)).decode()
 
 
-def mdhp_plan_create(offsets, t, dim, T, M: int, beta_mode: int = BETA_SHARED,
-                     device="cuda", stream=None) -> int:
-    """Validates and prepares a batch; returns the raw plan handle."""
-    lib = _lib.load()
+def _batch(offsets, t, dim, T, device):
+    """Device copies of a batch and its mdhp_batch descriptor (keep both alive)."""
     offsets = _dev(offsets, torch.int64, device)
     t = _dev(t, torch.float64, device)
     dim = _dev(dim, torch.int32, device)
     T = _dev(T, torch.float64, device)
     b = _lib.MdhpBatch(T.numel(), t.numel(), offsets.data_ptr(), t.data_ptr(), dim.data_ptr(),
                        T.data_ptr())
+    return (offsets, t, dim, T), b
+
+
+def mdhp_plan_create(offsets, t, dim, T, M: int, beta_mode: int = BETA_SHARED,
+                     device="cuda", stream=None) -> int:
+    """Validates and prepares a batch; returns the raw plan handle."""
+    lib = _lib.load()
+    _keep, b = _batch(offsets, t, dim, T, device)
     h = ctypes.c_void_p()
     _lib.check(lib.mdhp_plan_create(ctypes.byref(b), int(M), int(beta_mode),
                                     ctypes.c_void_p(_stream(stream)), ctypes.byref(h)))
@@ -110,6 +117,32 @@ def mdhp_fit_batch(handle, opts: FitOptions, mu, alpha, beta, ll, steps, status,
 def mdhp_cold_start(handle, mu, alpha, beta, stream=None) -> None:
     _lib.check(_lib.load().mdhp_cold_start(ctypes.c_void_p(handle), _ptr(mu), _ptr(alpha),
                                            _ptr(beta), ctypes.c_void_p(_stream(stream))))
+
+
+def mdhp_plan_autotune(handle, batch, opts: FitOptions | None, reps: int = 3,
+                       device="cuda", stream=None) -> dict:
+    """Times the plan's candidate schedules and keeps the fastest; batch is
+    (offsets, t, dim, T) of the plan.  Returns kind, values, ms and chosen."""
+    _keep, b = _batch(*batch, device)
+    r = _lib.MdhpTuneResult()
+    c = opts.to_c() if opts is not None else None
+    _lib.check(_lib.load().mdhp_plan_autotune(ctypes.c_void_p(handle), ctypes.byref(b),
+                                              ctypes.byref(c) if c is not None else None,
+                                              int(reps), ctypes.byref(r),
+                                              ctypes.c_void_p(_stream(stream))))
+    return dict(kind=int(r.kind), values=[int(r.value[i]) for i in range(r.n)],
+                ms=[float(r.ms[i]) for i in range(r.n)],
+                chosen=int(r.value[r.chosen]) if r.n else 0)
+
+
+def mdhp_plan_set_schedule(handle, batch, value: int, device="cuda", stream=None) -> None:
+    _keep, b = _batch(*batch, device)
+    _lib.check(_lib.load().mdhp_plan_set_schedule(ctypes.c_void_p(handle), ctypes.byref(b),
+                                                  int(value), ctypes.c_void_p(_stream(stream))))
+
+
+def mdhp_plan_schedule(handle) -> int:
+    return int(_lib.load().mdhp_plan_schedule(ctypes.c_void_p(handle)))
 
 
 def mdhp_check_params(handle, mu, alpha, beta, stream=None) -> None:
@@ -196,6 +229,20 @@ class Plan:
                            dtype=torch.float32, device=self.device)
         mdhp_cold_start(self.handle, mu, alpha, beta, stream)
         return mu, alpha, beta
+
+    def autotune(self, offsets, t, dim, T, opts: FitOptions | None = None, reps: int = 3,
+                 stream=None) -> dict:
+        """Keeps the fastest schedule for this plan's windows (mdhp_plan_autotune);
+        (offsets, t, dim, T) must be the batch the plan was made from."""
+        return mdhp_plan_autotune(self.handle, (offsets, t, dim, T), opts, reps, self.device,
+                                  stream)
+
+    def set_schedule(self, offsets, t, dim, T, value: int, stream=None) -> None:
+        mdhp_plan_set_schedule(self.handle, (offsets, t, dim, T), value, self.device, stream)
+
+    @property
+    def schedule(self) -> int:
+        return mdhp_plan_schedule(self.handle)
 
     def check_params(self, mu, alpha, beta, stream=None) -> None:
         mu, alpha, beta = self._params(mu, alpha, beta)

@@ -25,6 +25,8 @@ struct mdhp_plan {
   int32_t* counts = nullptr;  // [W][M] events per dimension
   int* counter = nullptr;  // window queue heads [2]
   int64_t n_big = 0;       // lane-major: windows run by a whole workgroup
+  int64_t big_min = 0;     // lane-major: events from which a window is run by a workgroup
+  int32_t scatter = 0;     // M > 16: events per reduce-scatter
   int* flags = nullptr;    // [0] error bits of prepare / check_params
   double* ll_ws = nullptr; // [2 W] likelihoods of the warm and cold starts
   float* fit_ws = nullptr; // L-BFGS per-workgroup vectors
@@ -67,12 +69,13 @@ mdhp_status hip_fail(hipError_t e, const char* where) { return mdhp_hip_fail(e, 
 // of the same window in FP64 (stored FP32; a positive gap never rounds to 0),
 // the u8 dimension id, and validation of order and domain.  With slot_begin
 // the window's events go lane-major: event k of a window of n events lands
-// in slot slot_begin[w] + L (k mod c) + k / c, with L = lane_team(n) chunks
+// in slot slot_begin[w] + L (k mod c) + k / c, with L = lane_team(n, big_min) chunks
 // and c = ceil(n / L), so that chunk l (events l c .. l c + c - 1) is read
 // a wave at a time.
 __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double* __restrict__ t,
                                const int32_t* __restrict__ dim, const double* __restrict__ T,
-                               const int64_t* __restrict__ slot_begin, int64_t W, int M,
+                               const int64_t* __restrict__ slot_begin, int64_t big_min,
+                               int64_t W, int M,
                                float* __restrict__ dt, uint8_t* __restrict__ d8,
                                float* __restrict__ end_gap, double* __restrict__ Tc,
                                int32_t* __restrict__ counts, int* flags) {
@@ -83,7 +86,7 @@ __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double
       __syncthreads();
     }
     const int64_t b = offsets[w], e = offsets[w + 1];
-    const int64_t L = lane_team(e - b);
+    const int64_t L = lane_team(e - b, big_min);
     const int64_t c = (e - b + L - 1) / L;
     const double Tw = T[w];
     int err = 0;
@@ -162,7 +165,8 @@ hipError_t eval_plan(const mdhp_plan* p, const float* mu, const float* alpha, co
     return pair_eval(ev, p->M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, p->counter, s, grad);
   if (p->lane_major)
     return lpc_eval(ev, p->M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, p->counter, s, grad);
-  return shared_eval(ev, p->M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, p->counter, s, grad);
+  return shared_eval(ev, p->M, p->scatter, mu, alpha, beta, ll, g_mu, g_alpha, g_beta,
+                     p->counter, s, grad);
 }
 
 Events events_of(const mdhp_plan* p) {
@@ -222,8 +226,13 @@ mdhp_status mdhp_last_error(char* buf, size_t n) {
   return g_last_status;
 }
 
-mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, void* stream,
-                             mdhp_plan** out) {
+}  // extern "C"
+
+namespace {
+
+// Validates and prepares a batch with lane-major team threshold big_min.
+mdhp_status build_plan(const mdhp_batch* b, int32_t M, int32_t beta_mode, int64_t big_min,
+                       hipStream_t s, mdhp_plan** out) {
   if (!out) return fail(MDHP_E_INVAL, "plan_create: out is NULL");
   *out = nullptr;
   if (!b) return fail(MDHP_E_INVAL, "plan_create: batch is NULL");
@@ -236,7 +245,6 @@ mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, 
   if (b->W > INT32_MAX) return fail(MDHP_E_INVAL, "plan_create: too many windows");
   if (!b->offsets || (b->W > 0 && !b->T) || (b->n_events > 0 && (!b->t || !b->dim)))
     return fail(MDHP_E_INVAL, "plan_create: null array");
-  hipStream_t s = (hipStream_t)stream;
   const int64_t W = b->W;
   std::vector<int64_t> off(W + 1);
   hipError_t e = hipMemcpyAsync(off.data(), b->offsets, (W + 1) * sizeof(int64_t),
@@ -257,18 +265,20 @@ mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, 
   p->M = M;
   p->beta_mode = beta_mode;
   p->magic = kMagic;
+  p->big_min = big_min;
+  p->scatter = kDefaultScatter;
   const int64_t N = b->n_events;
-  // Lane-major slots: L ceil(n_w / L) per window, L = lane_team(n_w).
+  // Lane-major slots: L ceil(n_w / L) per window, L = lane_team(n_w, big_min).
   p->lane_major = beta_mode == MDHP_BETA_SHARED && M <= kLaneMajorMaxM;
   std::vector<int64_t> sbeg;
   if (p->lane_major) {
     sbeg.resize(W);
     int64_t acc = 0;
     for (int64_t w = 0; w < W; ++w) {
-      const int64_t n = off[w + 1] - off[w], L = lane_team(n);
+      const int64_t n = off[w + 1] - off[w], L = lane_team(n, big_min);
       sbeg[w] = acc;
       acc += L * ((n + L - 1) / L);
-      if (n >= kBigWindow) ++p->n_big;
+      if (n >= big_min) ++p->n_big;
     }
     p->slots = acc;
   } else {
@@ -313,7 +323,7 @@ mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, 
     if (e == hipSuccess) {
       const int grid = (int)std::min<int64_t>(W, 65536);
       hipLaunchKernelGGL(prepare_kernel, dim3(grid), dim3(256), 0, s, b->offsets, b->t, b->dim,
-                         b->T, p->lane_major ? p->begin : nullptr, W, M, p->dt, p->d,
+                         b->T, p->lane_major ? p->begin : nullptr, p->big_min, W, M, p->dt, p->d,
                          p->end_gap, p->T, p->counts, p->flags);
       e = hipGetLastError();
     }
@@ -335,6 +345,15 @@ mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, 
   }
   *out = p;
   return MDHP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, void* stream,
+                             mdhp_plan** out) {
+  return build_plan(b, M, beta_mode, kBigWindow, (hipStream_t)stream, out);
 }
 
 void mdhp_plan_destroy(mdhp_plan* p) {
@@ -398,8 +417,8 @@ mdhp_status mdhp_fit_batch(mdhp_plan* p, const mdhp_fit_opts* o, float* mu, floa
           ? pair_fit(ev, p->M, fp, mu, alpha, beta, ll, steps, status, evals, p->counter, s)
       : p->lane_major ? lpc_fit(ev, p->M, fp, mu, alpha, beta, ll, steps, status, evals,
                                 p->fit_ws, p->fit_ws_floats, p->counter, s)
-                      : shared_fit(ev, p->M, fp, mu, alpha, beta, ll, steps, status, evals,
-                                   p->fit_ws, p->fit_ws_floats, p->counter, s);
+                      : shared_fit(ev, p->M, p->scatter, fp, mu, alpha, beta, ll, steps,
+                                   status, evals, p->fit_ws, p->fit_ws_floats, p->counter, s);
   if (e != hipSuccess) return hip_fail(e, "fit_batch: launch");
   return MDHP_OK;
 }
@@ -464,6 +483,144 @@ mdhp_status mdhp_check_params(mdhp_plan* p, const float* mu, const float* alpha,
   if (flags & kErrParam)
     return fail(MDHP_E_PARAM, "check_params: mu <= 0, alpha < 0, beta <= 0 or non-finite");
   return MDHP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Schedules a plan can be tuned to: kind 1, the events from which a
+// lane-major window is run by a whole workgroup; kind 2, the events per
+// reduce-scatter of the M > 16 kernels; kind 0, nothing (per-pair decays).
+int tune_candidates(const mdhp_plan* p, int32_t* kind, int32_t (&v)[MDHP_TUNE_MAX]) {
+  if (p->beta_mode != MDHP_BETA_SHARED) {
+    *kind = 0;
+    return 0;
+  }
+  if (p->lane_major) {
+    *kind = 1;
+    const int32_t c[] = {512, 1024, 2048, 4096, MDHP_TEAM_NEVER};
+    for (int i = 0; i < 5; ++i) v[i] = c[i];
+    return 5;
+  }
+  *kind = 2;
+  int n = 0;
+  for (int32_t b : {4, 8, 16})
+    if (shared_scatter_ok(p->M, b)) v[n++] = b;
+  return n;
+}
+
+// Switches the plan to schedule `value` of its kind; a new team threshold
+// re-prepares the batch (which must be the one the plan was made from).
+mdhp_status apply_schedule(mdhp_plan* p, const mdhp_batch* b, int32_t value, hipStream_t s) {
+  int32_t kind = 0, v[MDHP_TUNE_MAX];
+  const int n = tune_candidates(p, &kind, v);
+  bool known = false;
+  for (int i = 0; i < n; ++i) known = known || v[i] == value;
+  if (!known) return fail(MDHP_E_INVAL, "schedule: value is not a candidate of this plan");
+  if (kind == 2) {
+    p->scatter = value;
+    return MDHP_OK;
+  }
+  if ((int64_t)value == p->big_min) return MDHP_OK;
+  if (!b || b->W != p->W || b->n_events != p->N)
+    return fail(MDHP_E_INVAL, "schedule: the batch is not the plan's");
+  mdhp_plan* np = nullptr;
+  const mdhp_status st = build_plan(b, p->M, p->beta_mode, value, s, &np);
+  if (st != MDHP_OK) return st;
+  (void)hipStreamSynchronize(s);
+  std::swap(*p, *np);  // p takes the new layout; np holds the old buffers
+  free_plan(np);
+  return MDHP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mdhp_status mdhp_plan_set_schedule(mdhp_plan* p, const mdhp_batch* b, int32_t value,
+                                   void* stream) {
+  if (!plan_ok(p)) return fail(MDHP_E_INVAL, "set_schedule: invalid plan");
+  return apply_schedule(p, b, value, (hipStream_t)stream);
+}
+
+int32_t mdhp_plan_schedule(const mdhp_plan* p) {
+  if (!plan_ok(p) || p->beta_mode != MDHP_BETA_SHARED) return 0;
+  return p->lane_major ? (int32_t)std::min<int64_t>(p->big_min, MDHP_TEAM_NEVER) : p->scatter;
+}
+
+mdhp_status mdhp_plan_autotune(mdhp_plan* p, const mdhp_batch* b, const mdhp_fit_opts* o,
+                               int32_t reps, mdhp_tune_result* r, void* stream) {
+  if (!plan_ok(p)) return fail(MDHP_E_INVAL, "autotune: invalid plan");
+  if (!r || reps < 1) return fail(MDHP_E_INVAL, "autotune: bad result pointer or reps");
+  hipStream_t s = (hipStream_t)stream;
+  std::memset(r, 0, sizeof(*r));
+  int32_t kind = 0, v[MDHP_TUNE_MAX];
+  const int n = tune_candidates(p, &kind, v);
+  r->kind = kind;
+  if (n == 0 || p->W == 0) return MDHP_OK;
+  if (kind == 1 && (!b || b->W != p->W || b->n_events != p->N))
+    return fail(MDHP_E_INVAL, "autotune: the batch is not the plan's");
+  const int64_t W = p->W, M = p->M;
+  float *mu0 = nullptr, *al0 = nullptr, *be0 = nullptr, *mu = nullptr, *al = nullptr,
+        *be = nullptr, *gmu = nullptr, *gal = nullptr, *gbe = nullptr;
+  double* ll = nullptr;
+  int32_t *steps = nullptr, *status = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipSuccess;
+  auto cleanup = [&]() {
+    for (void* q : {(void*)mu0, (void*)al0, (void*)be0, (void*)mu, (void*)al, (void*)be,
+                    (void*)gmu, (void*)gal, (void*)gbe, (void*)ll, (void*)steps, (void*)status})
+      (void)hipFree(q);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if ((e = dev_alloc(&mu0, W * M)) != hipSuccess || (e = dev_alloc(&al0, W * M * M)) != hipSuccess ||
+      (e = dev_alloc(&be0, W)) != hipSuccess || (e = dev_alloc(&mu, W * M)) != hipSuccess ||
+      (e = dev_alloc(&al, W * M * M)) != hipSuccess || (e = dev_alloc(&be, W)) != hipSuccess ||
+      (e = dev_alloc(&gmu, W * M)) != hipSuccess || (e = dev_alloc(&gal, W * M * M)) != hipSuccess ||
+      (e = dev_alloc(&gbe, W)) != hipSuccess || (e = dev_alloc(&ll, W)) != hipSuccess ||
+      (e = dev_alloc(&steps, W)) != hipSuccess || (e = dev_alloc(&status, W)) != hipSuccess ||
+      (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "autotune: allocation");
+  }
+  mdhp_status st = MDHP_OK;
+  int best = -1;
+  for (int i = 0; i < n && st == MDHP_OK; ++i) {
+    st = apply_schedule(p, b, v[i], s);
+    if (st != MDHP_OK) break;
+    st = mdhp_cold_start(p, mu0, al0, be0, s);
+    float total = 0.f;
+    for (int rep = 0; rep <= reps && st == MDHP_OK; ++rep) {  // rep 0 warms up
+      if (o) {
+        e = hipMemcpyAsync(mu, mu0, W * M * sizeof(float), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(al, al0, W * M * M * sizeof(float), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(be, be0, W * sizeof(float), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) break;
+      }
+      if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+      st = o ? mdhp_fit_batch(p, o, mu, al, be, ll, steps, status, nullptr, s)
+             : mdhp_grad(p, mu0, al0, be0, ll, gmu, gal, gbe, s);
+      if (st != MDHP_OK) break;
+      if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess)
+        break;
+      float ms = 0.f;
+      if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+      if (rep > 0) total += ms;
+    }
+    if (e != hipSuccess && st == MDHP_OK) st = hip_fail(e, "autotune: timing");
+    r->value[i] = v[i];
+    r->ms[i] = total / reps;
+    r->n = i + 1;
+    if (st == MDHP_OK && (best < 0 || r->ms[i] < r->ms[best])) best = i;
+  }
+  cleanup();
+  if (st != MDHP_OK) return st;
+  r->chosen = best;
+  return apply_schedule(p, b, v[best], s);
 }
 
 }  // extern "C"

@@ -75,10 +75,15 @@ inline void reset_counter(int* counter, hipStream_t s) {
 #endif
 // Largest M whose shared-decay plans use the lane-major layout and kernels.
 constexpr int kLaneMajorMaxM = MDHP_LANE_MAJOR_MAX_M;
-// Lane-major windows of at least this many events are laid out for, and
-// run by, a whole workgroup (256 chunks); shorter ones by one wavefront (64).
+// Lane-major windows of at least big_min events are laid out for, and run
+// by, a whole workgroup (256 chunks); shorter ones by one wavefront (64).
+// The default threshold; a plan can be tuned to another.
 constexpr int64_t kBigWindow = 1024;
-__host__ __device__ inline int64_t lane_team(int64_t n) { return n >= kBigWindow ? kBlock : 64; }
+// Default events per reduce-scatter of the M > 16 kernels.
+constexpr int kDefaultScatter = 8;
+__host__ __device__ inline int64_t lane_team(int64_t n, int64_t big_min) {
+  return n >= big_min ? kBlock : 64;
+}
 
 // Lane-major (one chunk per lane, one window per wave) kernels, M <= 16.
 hipError_t lpc_eval(const Events& ev, int M, const float* mu, const float* alpha,
@@ -90,12 +95,14 @@ hipError_t lpc_fit(const Events& ev, int M, const FitParams& o, float* mu, float
 int64_t lpc_lbfgs_workspace(int M, int64_t W, int64_t n_big);
 
 // Workgroup-per-window kernels for the compact layout, 16 < M <= 64.
-hipError_t shared_eval(const Events& ev, int M, const float* mu, const float* alpha,
+// scatter: events per reduce-scatter (M > 16; see shared_scatter_ok).
+hipError_t shared_eval(const Events& ev, int M, int scatter, const float* mu, const float* alpha,
                        const float* beta, double* ll, float* g_mu, float* g_alpha, float* g_beta,
                        int* counter, hipStream_t s, bool grad);
-hipError_t shared_fit(const Events& ev, int M, const FitParams& o, float* mu, float* alpha,
-                      float* beta, double* ll, int* steps, int* status, int* evals, float* ws,
-                      int64_t ws_floats, int* counter, hipStream_t s);
+hipError_t shared_fit(const Events& ev, int M, int scatter, const FitParams& o, float* mu,
+                      float* alpha, float* beta, double* ll, int* steps, int* status, int* evals,
+                      float* ws, int64_t ws_floats, int* counter, hipStream_t s);
+bool shared_scatter_ok(int M, int scatter);
 // Floats of workspace the L-BFGS fit needs for a plan of W windows.
 int64_t shared_lbfgs_workspace(int M, int64_t W);
 hipError_t pair_eval(const Events& ev, int M, const float* mu, const float* alpha,

@@ -47,11 +47,9 @@ namespace {
 #endif
 // Events per pass-2 batch (at most the group size).
 constexpr int kBatch = MDHP_BATCH;
-#ifndef MDHP_SCATTER
-#define MDHP_SCATTER 8
-#endif
-// Events per reduce-scatter for groups of 32 or 64 lanes.
-constexpr int kScatter = MDHP_SCATTER;
+// Events per reduce-scatter for groups of 32 or 64 lanes: the default, and
+// the choices a plan can be tuned to.
+constexpr int kScatter = kDefaultScatter;
 
 typedef float f32x32 __attribute__((ext_vector_type(32)));
 
@@ -141,7 +139,7 @@ __device__ __forceinline__ float group_reduce_scatter(float (&v)[B]) {
 // colsum, beta).  Results: sh.scal[0] = ll, and if GRAD: gR64[k] holds
 // G_R[e] for e = tid + k * kBlock (FP64), sh.Cn, sh.Fn, sh.gmu (= d ll/d mu),
 // sh.scal[1] = d ll / d beta.  cnt_w: the window's events per dimension.
-template <int P, bool GRAD>
+template <int P, bool GRAD, int SB>
 __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __restrict__ dtg,
                             const uint8_t* __restrict__ dg, int64_t begin, int n, double T,
                             float end_gap, int M, const int32_t* __restrict__ cnt_w,
@@ -248,7 +246,7 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
     // the recursion with broadcast reads of the staged values, one
     // reduce-scatter for their intensities, log and reciprocal there, and
     // the G_R row adds.
-    constexpr int B = kScatter;
+    constexpr int B = SB;
     constexpr int SH = P == 64 ? (B == 16 ? 2 : B == 8 ? 3 : 4) : (B == 16 ? 1 : B == 8 ? 2 : 3);
     const int ev_l = lane >> SH;                 // the event whose intensity this lane gets
     const bool lead = (lane & ((1 << SH) - 1)) == 0;
@@ -528,7 +526,7 @@ __device__ int next_window(SharedLds<P>& sh, int* counter, int first) {
   return sh.next_window;
 }
 
-template <int P, bool GRAD>
+template <int P, bool GRAD, int SB>
 __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_eval_kernel(Events ev, int M, const float* mu,
                                                              const float* alpha,
                                                              const float* beta, double* ll,
@@ -543,7 +541,7 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_eva
     const int64_t w = ev.order[q];
     load_params(sh, mu, alpha, beta, w, M);
     const double T = ev.T[w];
-    eval_window<P, GRAD>(sh, ev.dt, ev.d, ev.begin[w], ev.n[w], T, ev.end_gap[w], M, ev.counts + w * M, gR64);
+    eval_window<P, GRAD, SB>(sh, ev.dt, ev.d, ev.begin[w], ev.n[w], T, ev.end_gap[w], M, ev.counts + w * M, gR64);
     if (tid == 0) ll[w] = sh.scal[0];
     if constexpr (GRAD) {
       if (tid == 0) g_beta[w] = (float)sh.scal[1];
@@ -560,7 +558,7 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_eva
 }
 
 // Persistent projected-gradient fit (see mdhp_fit_opts for the rule).
-template <int P>
+template <int P, int SB>
 __global__ __launch_bounds__(kBlock, (P == 32 ? 2 : kMinBlocks)) void shared_fit_kernel(Events ev, int M, FitParams o,
                                                             float* mu, float* alpha, float* beta,
                                                             double* ll, int* steps, int* status,
@@ -586,7 +584,7 @@ __global__ __launch_bounds__(kBlock, (P == 32 ? 2 : kMinBlocks)) void shared_fit
     double ll_prev = 0.0, b1t = 1.0, b2t = 1.0;
     int s = 0, st = MDHP_FIT_MAX_STEPS;
     for (s = 0;; ++s) {
-      eval_window<P, true>(sh, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], M, ev.counts + w * M, gR64);
+      eval_window<P, true, SB>(sh, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], M, ev.counts + w * M, gR64);
       const double l = sh.scal[0];
       // Finiteness of ll and of the whole gradient (one flag per block).
       if (tid == 0) sh.stop = isfinite(l) && isfinite(sh.scal[1]) ? 0 : 1;
@@ -700,7 +698,7 @@ __device__ __forceinline__ double block_max_abs(double v, double* scratch) {
 // pairs live in a per-workgroup region of the global workspace that only it
 // reads and writes; the scalars of the two-loop recursion come from block
 // reductions.
-template <int P>
+template <int P, int SB>
 __global__ __launch_bounds__(kBlock, (P == 32 ? 2 : kMinBlocks)) void shared_lbfgs_kernel(Events ev, int M, FitParams o,
                                                               float* mu, float* alpha,
                                                               float* beta, double* ll,
@@ -782,7 +780,7 @@ __global__ __launch_bounds__(kBlock, (P == 32 ? 2 : kMinBlocks)) void shared_lbf
     };
     // Evaluates at the LDS parameters; true if ll and the gradient are finite.
     auto evaluate = [&]() -> bool {
-      eval_window<P, true>(sh, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], M, ev.counts + w * M, gR64);
+      eval_window<P, true, SB>(sh, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], M, ev.counts + w * M, gR64);
       if (tid == 0) flag = isfinite(sh.scal[0]) && isfinite(sh.scal[1]) ? 0 : 1;
       __syncthreads();
       bool bad = false;
@@ -951,25 +949,25 @@ __global__ __launch_bounds__(kBlock, (P == 32 ? 2 : kMinBlocks)) void shared_lbf
   }
 }
 
-template <int P>
+template <int P, int SB>
 hipError_t launch_shared_eval(const Events& ev, int M, const float* mu, const float* alpha,
                               const float* beta, double* ll, float* g_mu, float* g_alpha,
                               float* g_beta, int* counter, hipStream_t s, bool grad) {
   if (ev.W == 0) return hipSuccess;
   reset_counter(counter, s);
   if (grad) {
-    auto k = shared_eval_kernel<P, true>;
+    auto k = shared_eval_kernel<P, true, SB>;
     hipLaunchKernelGGL(k, dim3(occupancy_grid(k, kBlock, ev.W)), dim3(kBlock), 0, s, ev, M, mu, alpha,
                        beta, ll, g_mu, g_alpha, g_beta, counter);
   } else {
-    auto k = shared_eval_kernel<P, false>;
+    auto k = shared_eval_kernel<P, false, SB>;
     hipLaunchKernelGGL(k, dim3(occupancy_grid(k, kBlock, ev.W)), dim3(kBlock), 0, s, ev, M, mu, alpha,
                        beta, ll, g_mu, g_alpha, g_beta, counter);
   }
   return hipGetLastError();
 }
 
-template <int P>
+template <int P, int SB>
 hipError_t launch_shared_fit(const Events& ev, int M, const FitParams& o, float* mu,
                              float* alpha, float* beta, double* ll, int* steps, int* status,
                              int* evals, float* ws, int64_t ws_floats, int* counter,
@@ -977,7 +975,7 @@ hipError_t launch_shared_fit(const Events& ev, int M, const FitParams& o, float*
   if (ev.W == 0) return hipSuccess;
   reset_counter(counter, s);
   if (o.optimizer == MDHP_OPT_LBFGS) {
-    auto k = shared_lbfgs_kernel<P>;
+    auto k = shared_lbfgs_kernel<P, SB>;
     const int64_t per_block = (int64_t)(4 + 2 * kMaxHistory) * (own_count(P) + 1) * kBlock;
     const int grid = (int)std::min<int64_t>(occupancy_grid(k, kBlock, ev.W), ws_floats / per_block);
     if (grid < 1) return hipErrorInvalidValue;
@@ -985,52 +983,73 @@ hipError_t launch_shared_fit(const Events& ev, int M, const FitParams& o, float*
                        status, evals, ws, counter);
     return hipGetLastError();
   }
-  auto k = shared_fit_kernel<P>;
+  auto k = shared_fit_kernel<P, SB>;
   hipLaunchKernelGGL(k, dim3(occupancy_grid(k, kBlock, ev.W)), dim3(kBlock), 0, s, ev, M, o, mu,
                      alpha, beta, ll, steps, status, evals, counter);
   return hipGetLastError();
 }
 
-template <int P>
+template <int P, int SB>
 int64_t shared_lbfgs_ws(int64_t W) {
   const int64_t per_block = (int64_t)(4 + 2 * kMaxHistory) * (own_count(P) + 1) * kBlock;
-  return per_block * occupancy_grid(shared_lbfgs_kernel<P>, kBlock, std::max<int64_t>(W, 1));
+  return per_block * occupancy_grid(shared_lbfgs_kernel<P, SB>, kBlock, std::max<int64_t>(W, 1));
+}
+
+// Calls f(std::integral_constant<int, P>, std::integral_constant<int, B>) for
+// the plan's group width P and reduce-scatter width B (B matters for P >= 32
+// only; other widths fall back to the default).
+template <class F>
+auto with_shape(int M, int scatter, F&& f) {
+  using std::integral_constant;
+  switch (lanes_for(M)) {
+    case 4: return f(integral_constant<int, 4>{}, integral_constant<int, kScatter>{});
+    case 8: return f(integral_constant<int, 8>{}, integral_constant<int, kScatter>{});
+    case 16: return f(integral_constant<int, 16>{}, integral_constant<int, kScatter>{});
+    case 32:
+      if (scatter == 4) return f(integral_constant<int, 32>{}, integral_constant<int, 4>{});
+      return f(integral_constant<int, 32>{}, integral_constant<int, 8>{});
+    default:
+      if (scatter == 4) return f(integral_constant<int, 64>{}, integral_constant<int, 4>{});
+      if (scatter == 16) return f(integral_constant<int, 64>{}, integral_constant<int, 16>{});
+      return f(integral_constant<int, 64>{}, integral_constant<int, 8>{});
+  }
 }
 
 }  // namespace
 
-hipError_t shared_eval(const Events& ev, int M, const float* mu, const float* alpha,
+hipError_t shared_eval(const Events& ev, int M, int scatter, const float* mu, const float* alpha,
                        const float* beta, double* ll, float* g_mu, float* g_alpha, float* g_beta,
                        int* counter, hipStream_t s, bool grad) {
-  switch (lanes_for(M)) {
-    case 4: return launch_shared_eval<4>(ev, M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, counter, s, grad);
-    case 8: return launch_shared_eval<8>(ev, M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, counter, s, grad);
-    case 16: return launch_shared_eval<16>(ev, M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, counter, s, grad);
-    case 32: return launch_shared_eval<32>(ev, M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, counter, s, grad);
-    default: return launch_shared_eval<64>(ev, M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, counter, s, grad);
-  }
+  return with_shape(M, scatter, [&](auto P, auto B) {
+    return launch_shared_eval<P(), B()>(ev, M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta,
+                                        counter, s, grad);
+  });
 }
 
-hipError_t shared_fit(const Events& ev, int M, const FitParams& o, float* mu, float* alpha,
-                      float* beta, double* ll, int* steps, int* status, int* evals, float* ws,
-                      int64_t ws_floats, int* counter, hipStream_t s) {
-  switch (lanes_for(M)) {
-    case 4: return launch_shared_fit<4>(ev, M, o, mu, alpha, beta, ll, steps, status, evals, ws, ws_floats, counter, s);
-    case 8: return launch_shared_fit<8>(ev, M, o, mu, alpha, beta, ll, steps, status, evals, ws, ws_floats, counter, s);
-    case 16: return launch_shared_fit<16>(ev, M, o, mu, alpha, beta, ll, steps, status, evals, ws, ws_floats, counter, s);
-    case 32: return launch_shared_fit<32>(ev, M, o, mu, alpha, beta, ll, steps, status, evals, ws, ws_floats, counter, s);
-    default: return launch_shared_fit<64>(ev, M, o, mu, alpha, beta, ll, steps, status, evals, ws, ws_floats, counter, s);
-  }
+hipError_t shared_fit(const Events& ev, int M, int scatter, const FitParams& o, float* mu,
+                      float* alpha, float* beta, double* ll, int* steps, int* status, int* evals,
+                      float* ws, int64_t ws_floats, int* counter, hipStream_t s) {
+  return with_shape(M, scatter, [&](auto P, auto B) {
+    return launch_shared_fit<P(), B()>(ev, M, o, mu, alpha, beta, ll, steps, status, evals, ws,
+                                       ws_floats, counter, s);
+  });
 }
 
 int64_t shared_lbfgs_workspace(int M, int64_t W) {
-  switch (lanes_for(M)) {
-    case 4: return shared_lbfgs_ws<4>(W);
-    case 8: return shared_lbfgs_ws<8>(W);
-    case 16: return shared_lbfgs_ws<16>(W);
-    case 32: return shared_lbfgs_ws<32>(W);
-    default: return shared_lbfgs_ws<64>(W);
-  }
+  // Enough for every reduce-scatter width the plan may be tuned to.
+  int64_t most = 0;
+  for (int b : {4, 8, 16})
+    most = std::max(most, with_shape(M, b, [&](auto P, auto B) {
+      return shared_lbfgs_ws<P(), B()>(W);
+    }));
+  return most;
+}
+
+bool shared_scatter_ok(int M, int scatter) {
+  const int p = lanes_for(M);
+  if (p == 64) return scatter == 4 || scatter == 8 || scatter == 16;
+  if (p == 32) return scatter == 4 || scatter == 8;
+  return scatter == kScatter;
 }
 
 }  // namespace mdhp
