@@ -223,6 +223,8 @@ def main() -> int:
     ap.add_argument("--no-warm", action="store_true", help="time cold-start fits only")
     ap.add_argument("--cpu-sample", type=int, default=96)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default schedule instead of tuning it on the batch first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (5 times), "
                          "the reference for scaling HBM traffic counters")
@@ -255,8 +257,9 @@ def main() -> int:
     if args.workload == "pair_m32":
         return bench_pair(args, dev)
     if args.workload == "large_m64":
-        args.no_warm = True
-        args.no_gds = True
+        args.no_gds = True  # 500 projected Adam updates of 151M events: minutes per run
+        if args.train_windows == 65536:
+            args.train_windows = 4096
         if args.windows == 4096:
             args.windows = 16384
         if args.cpu_sample == 96:
@@ -288,12 +291,28 @@ def main() -> int:
                       "loss_first_last": [losses[0], losses[-1]],
                       "total_s": time.perf_counter() - t0}
 
+    # Schedule autotuning (untimed, like the network's training): the plan's
+    # candidate schedules timed on this batch with the main fit rule.
+    plan = mdhp.Plan(db.offsets, db.t, db.dim, db.T, b.M, mdhp.BETA_SHARED, device=dev)
+    default_schedule = plan.schedule
+    tuned, tune_info = default_schedule, None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        r = plan.autotune(db.offsets, db.t, db.dim, db.T, mdhp.FitOptions(**main_kw), reps=1)
+        tune_info = dict(r, seconds=time.perf_counter() - t0, default=default_schedule,
+                         objective="one fit of the batch from the cold start with the main "
+                                   "rule per candidate, after one untimed fit")
+        tuned = r["chosen"]
+    plan.close()
+
     def step(warm, opts_kw, events=None):
         """One pass of the whole path: plan, initial point, fit."""
         opts = mdhp.FitOptions(**opts_kw)
         if events is not None:
             events[0].record()
         plan = mdhp.Plan(db.offsets, db.t, db.dim, db.T, b.M, mdhp.BETA_SHARED, device=dev)
+        if tuned != default_schedule:
+            plan.set_schedule(db.offsets, db.t, db.dim, db.T, tuned)
         if warm:
             mu, al, be, used, _ = warmstart.warm_init(db, net, opts, plan)
         else:
@@ -342,6 +361,36 @@ def main() -> int:
     main_label = ("warm_" if net is not None else "cold_") + (
         "lbfgs" if args.optimizer == "lbfgs" else "gds")
     main_run = runs[main_label]
+
+    # The main pipeline (initial point + fit, on a prepared plan) eagerly and
+    # as one captured HIP graph.
+    from paper_2411_10258_amd import graph
+    plan = mdhp.Plan(db.offsets, db.t, db.dim, db.T, b.M, mdhp.BETA_SHARED, device=dev)
+    if tuned != default_schedule:
+        plan.set_schedule(db.offsets, db.t, db.dim, db.T, tuned)
+    gopts = mdhp.FitOptions(**main_kw)
+    gnet = net if main_label.startswith("warm") else None
+    gbatch = (db.offsets, db.t, db.dim, db.T)
+    extra = {} if gnet is None else dict(mean=torch.from_numpy(net.stats.mean).to(dev),
+                                         std=torch.from_numpy(net.stats.std).to(dev))
+    graph.fit_pipeline(plan, gopts, gnet, gbatch, **extra)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.fit_pipeline(plan, gopts, gnet, gbatch, **extra)
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    g = graph.FitGraph(plan, gopts, gnet, gbatch)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph_info = {"pipeline": main_label.replace("_", " start + ") + " fit on a prepared plan",
+                  "eager_ms": eager_ms, "replay_ms": (time.perf_counter() - t0) * 1e3 / args.steps}
+    del g
+    plan.close()
 
     # Reference optimum (untimed): a long L-BFGS run from the cold start
     # (memory 16, no likelihood stop); a window's optimum is the best
@@ -430,6 +479,8 @@ def main() -> int:
         out["warm_speedup_same_rule"] = rate(main_run) / max(
             rate(runs["cold_" + main_label.split("_")[1]]), 1e-30)
         out["surrogate_training"] = train_info
+    out["schedule"] = tune_info if tune_info is not None else {"default": default_schedule}
+    out["graph"] = graph_info
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(b, main_kw, args.cpu_sample, main_run["params"],
                                            lstar_ref, scale)

@@ -24,16 +24,17 @@ def test_features_match_reference(gpu, synth_lib):
     assert np.mean(x == ref) > 0.99
 
 
-def _net(gpu, seed=3, max_batch=256):
+def _net(gpu, seed=3, max_batch=256, M=16):
     from paper_2411_10258_amd import surrogate
-    return surrogate.Surrogate(16, hidden=512, max_batch=max_batch, seed=seed)
+    return surrogate.Surrogate(M, hidden=512, max_batch=max_batch, seed=seed)
 
 
-def test_forward_matches_reference(gpu):
+@pytest.mark.parametrize("M", [16, 64])
+def test_forward_matches_reference(gpu, M):
     import torch
-    net = _net(gpu)
+    net = _net(gpu, M=M)
     rng = np.random.default_rng(0)
-    B = 200  # ragged against the 64-row tiles
+    B = 200 if M == 16 else 72  # ragged against the 64-row tiles
     x = mlp.bf16(np.abs(rng.standard_normal((B, net.in_dim))))
     print("[surrogate] forward", flush=True)
     y = net.forward(_bf16_tensor(x)).cpu().numpy()
