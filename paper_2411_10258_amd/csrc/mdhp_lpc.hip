@@ -2,10 +2,10 @@
 // chunk of events per lane ("lane per chunk").
 //
 // A team of NW wavefronts owns one window at a time: one wavefront for
-// ordinary windows, the whole 4-wave workgroup for windows of at least
-// kBigWindow events.  Those come first in the largest-first order, so a
-// persistent workgroup takes big windows as a team, then its waves take the
-// rest one each.  The window's N events are cut into T = 64 NW contiguous
+// ordinary windows, the whole 4-wave workgroup for windows of at least the
+// plan's threshold (1,024 events unless tuned).  Those form a prefix of the
+// largest-first order; persistent workgroups take them as teams and their
+// waves take the rest one each (see for_windows).  The window's N events are cut into T = 64 NW contiguous
 // chunks of c = ceil(N / T) events, one per lane of the team, and the plan
 // stores them lane-major: event j of chunk t sits at slot begin + T j + t
 // (padding slots: gap 0, dimension 0xFF), so every step of a wave reads 64
@@ -159,6 +159,36 @@ struct alignas(16) Team {
   float beta;
 };
 
+// One-hot rows e_m (m < MP) and a zero row MP for the recursion's newly
+// pending event: the add of [d = m] to R_m + P_m becomes one 16-byte row read
+// per four components instead of a compare and select per component.  Rows
+// are kOhStride floats apart (distinct bank groups for neighbouring rows).
+constexpr int kOhStride = 20;
+__shared__ float4 g_onehot[(16 + 1) * kOhStride / 4];
+
+template <int MP>
+__device__ __forceinline__ void onehot_init() {
+  float* oh = reinterpret_cast<float*>(g_onehot);
+  for (int e = threadIdx.x; e < (MP + 1) * kOhStride; e += blockDim.x) {
+    const int r = e / kOhStride, m = e % kOhStride;
+    oh[e] = (r < MP && m == r) ? 1.f : 0.f;
+  }
+}
+
+// Row d of the table (the zero row for d >= MP, e.g. a padding slot).
+template <int MP>
+__device__ __forceinline__ void onehot_row(int d, float (&oh)[MP]) {
+  const float4* row = &g_onehot[(d < MP ? d : MP) * (kOhStride / 4)];
+#pragma unroll
+  for (int q = 0; q < MP / 4; ++q) {
+    const float4 v = row[q];
+    oh[4 * q] = v.x;
+    oh[4 * q + 1] = v.y;
+    oh[4 * q + 2] = v.z;
+    oh[4 * q + 3] = v.w;
+  }
+}
+
 template <int NW>
 __device__ __forceinline__ int team_tid() {
   return threadIdx.x & (64 * NW - 1);
@@ -311,10 +341,12 @@ __device__ __forceinline__ void team_eval(Team<MP, NW>& sh, const float* __restr
   cr.D = 0.f;
   for_steps<T>(dtw, dw, c, [&](int, float dt, int d) {
     const float a = dt > 0.f ? __expf(-beta * dt) : 1.f;
+    float oh[MP];
+    onehot_row<MP>(d, oh);
 #pragma unroll
     for (int m = 0; m < MP; ++m) {
       cr.S[m] = a * fmaf(dt, Rin[m], cr.S[m]);
-      Rin[m] = fmaf(a, Rin[m], m == d ? 1.f : 0.f);
+      Rin[m] = fmaf(a, Rin[m], oh[m]);
     }
     cr.A *= a;
     cr.D += dt;
@@ -459,12 +491,14 @@ __device__ __forceinline__ void team_eval(Team<MP, NW>& sh, const float* __restr
     float lam = sh.mu[d], asum = 0.f;
     float g_old = 0.f;
     if constexpr (GRAD) g_old = gmu[d * GS];
+    float oh[MP];
+    onehot_row<MP>(dr, oh);
 #pragma unroll
     for (int m = 0; m < MP; ++m) {
       const float tm = a * Rin[m];
       S[m] = a * fmaf(dt, Rin[m], S[m]);
       R[m] = f ? tm : R[m];
-      Rin[m] = tm + (m == dr ? 1.f : 0.f);
+      Rin[m] = tm + oh[m];
       const float al = arow[m];
       lam = fmaf(al, R[m], lam);
       asum = fmaf(al, S[m], asum);
@@ -612,29 +646,42 @@ union BlockLds {
   Team<MP, 1> small[kWaves];
 };
 
-// Runs body(team LDS, window) over the big windows (team = workgroup), then
-// over the rest (team = wavefront).  counter[0] and counter[1] are the heads
-// of the two queues.
+// Runs every window once: the first n_big of the largest-first order as
+// workgroup teams (queue head counter[0], largest first), the rest one per
+// wavefront (counter[1], smallest first).  One workgroup in kSmallFirst
+// starts with the one-wave windows, the others with the workgroup windows;
+// each turns to the other queue when its first is empty.  Small windows are
+// cheap per evaluation but some need many evaluations, so they start from
+// the beginning instead of after every large window, and the longest of
+// them no longer ends the batch.
+constexpr int kSmallFirst = 4;
 template <int MP, class BIG, class SMALL>
 __device__ __forceinline__ void for_windows(BlockLds<MP>& lds, const Events& ev, int* counter,
                                             BIG&& big_body, SMALL&& small_body) {
   const int nb = (int)ev.n_big;
-  {
+  const int W = (int)ev.W;
+  auto big_phase = [&]() {
     Team<MP, kWaves>& sh = lds.big;
     team_init(sh);
-    for (int q = team_next(sh, &counter[0], true, (int)blockIdx.x, (int)gridDim.x); q < nb;
-         q = team_next(sh, &counter[0], false, 0, (int)gridDim.x))
+    for (int q = team_next(sh, &counter[0], false, 0, 0); q < nb;
+         q = team_next(sh, &counter[0], false, 0, 0))
       big_body(sh, (int64_t)ev.order[q]);
     __syncthreads();
-  }
-  {
-    const int wave = threadIdx.x >> 6;
-    Team<MP, 1>& sh = lds.small[wave];
+  };
+  auto small_phase = [&]() {
+    Team<MP, 1>& sh = lds.small[threadIdx.x >> 6];
     team_init(sh);
-    const int started = (int)gridDim.x * kWaves;
-    for (int q = nb + team_next(sh, &counter[1], true, (int)blockIdx.x * kWaves + wave, started);
-         q < ev.W; q = nb + team_next(sh, &counter[1], false, 0, started))
-      small_body(sh, (int64_t)ev.order[q]);
+    for (int k = team_next(sh, &counter[1], false, 0, 0); nb + k < W;
+         k = team_next(sh, &counter[1], false, 0, 0))
+      small_body(sh, (int64_t)ev.order[W - 1 - k]);
+    __syncthreads();
+  };
+  if ((int)blockIdx.x % kSmallFirst == kSmallFirst - 1) {
+    small_phase();
+    big_phase();
+  } else {
+    big_phase();
+    small_phase();
   }
 }
 
@@ -670,6 +717,8 @@ __global__ __launch_bounds__(kBlock, 2) void lpc_eval_kernel(Events ev, int M, c
                                                           float* g_alpha, float* g_beta,
                                                           int* counter) {
   __shared__ BlockLds<MP> lds;
+  onehot_init<MP>();
+  __syncthreads();
   for_windows<MP>(
       lds, ev, counter,
       [&](Team<MP, kWaves>& sh, int64_t w) {
@@ -826,6 +875,8 @@ __global__ __launch_bounds__(kBlock, 2) void lpc_fit_kernel(Events ev, int M, Fi
                                                          double* ll, int* steps, int* status,
                                                          int* evals_out, int* counter) {
   __shared__ BlockLds<MP> lds;
+  onehot_init<MP>();
+  __syncthreads();
   for_windows<MP>(
       lds, ev, counter,
       [&](Team<MP, kWaves>& sh, int64_t w) {
@@ -1072,6 +1123,8 @@ __global__ __launch_bounds__(kBlock, 2) void lpc_lbfgs_kernel(Events ev, int M, 
                                                            int* evals_out, float* ws,
                                                            int* counter) {
   __shared__ BlockLds<MP> lds;
+  onehot_init<MP>();
+  __syncthreads();
   float* blk = ws + (size_t)blockIdx.x * (size_t)block_ws<MP>();
   for_windows<MP>(
       lds, ev, counter,
