@@ -79,10 +79,16 @@ constexpr int kLaneMajorMaxM = MDHP_LANE_MAJOR_MAX_M;
 // by, a whole workgroup (256 chunks); shorter ones by one wavefront (64).
 // The default threshold; a plan can be tuned to another.
 constexpr int64_t kBigWindow = 1024;
+#ifndef MDHP_LPC_WAVES
+#define MDHP_LPC_WAVES 4
+#endif
+// Workgroup of the lane-major kernels: MDHP_LPC_WAVES wavefronts, the team
+// that runs a window of at least big_min events.
+constexpr int kLpcBlock = 64 * MDHP_LPC_WAVES;
 // Default events per reduce-scatter of the M > 16 kernels.
 constexpr int kDefaultScatter = 8;
 __host__ __device__ inline int64_t lane_team(int64_t n, int64_t big_min) {
-  return n >= big_min ? kBlock : 64;
+  return n >= big_min ? kLpcBlock : 64;
 }
 
 // Lane-major (one chunk per lane, one window per wave) kernels, M <= 16.

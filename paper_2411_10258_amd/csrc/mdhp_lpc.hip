@@ -46,7 +46,8 @@ namespace mdhp {
 
 namespace {
 
-constexpr int kWaves = kBlock / 64;  // wavefronts per workgroup
+constexpr int kWaves = kLpcBlock / 64;  // wavefronts per workgroup
+constexpr int kMinBlocksLpc = 8 / kWaves;  // workgroups per CU: 2 waves per SIMD
 constexpr int kPad = 0xFF;           // dimension byte of a padding slot
 constexpr int kSpan = 16;            // steps per FP32 span of the MFMA sums
 
@@ -711,7 +712,7 @@ __device__ __forceinline__ void eval_one(Team<MP, NW>& sh, const Events& ev, int
 }
 
 template <int MP, bool GRAD>
-__global__ __launch_bounds__(kBlock, 2) void lpc_eval_kernel(Events ev, int M, const float* mu,
+__global__ __launch_bounds__(kLpcBlock, kMinBlocksLpc) void lpc_eval_kernel(Events ev, int M, const float* mu,
                                                           const float* alpha, const float* beta,
                                                           double* ll, float* g_mu,
                                                           float* g_alpha, float* g_beta,
@@ -870,7 +871,7 @@ __device__ __forceinline__ void fit_one(Team<MP, NW>& sh, const Events& ev, int6
 }
 
 template <int MP>
-__global__ __launch_bounds__(kBlock, 2) void lpc_fit_kernel(Events ev, int M, FitParams o,
+__global__ __launch_bounds__(kLpcBlock, kMinBlocksLpc) void lpc_fit_kernel(Events ev, int M, FitParams o,
                                                          float* mu, float* alpha, float* beta,
                                                          double* ll, int* steps, int* status,
                                                          int* evals_out, int* counter) {
@@ -1117,7 +1118,7 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
 }
 
 template <int MP>
-__global__ __launch_bounds__(kBlock, 2) void lpc_lbfgs_kernel(Events ev, int M, FitParams o,
+__global__ __launch_bounds__(kLpcBlock, kMinBlocksLpc) void lpc_lbfgs_kernel(Events ev, int M, FitParams o,
                                                            float* mu, float* alpha, float* beta,
                                                            double* ll, int* steps, int* status,
                                                            int* evals_out, float* ws,
@@ -1143,7 +1144,7 @@ __global__ __launch_bounds__(kBlock, 2) void lpc_lbfgs_kernel(Events ev, int M, 
 template <class KERN>
 int lpc_grid(KERN k, int64_t W, int64_t n_big) {
   const int64_t want = std::max<int64_t>(n_big, (W - n_big + kWaves - 1) / kWaves);
-  return occupancy_grid(k, kBlock, std::max<int64_t>(want, 1));
+  return occupancy_grid(k, kLpcBlock, std::max<int64_t>(want, 1));
 }
 
 template <int MP>
@@ -1154,11 +1155,11 @@ hipError_t launch_lpc_eval(const Events& ev, int M, const float* mu, const float
   reset_counter(counter, s);
   if (grad) {
     auto k = lpc_eval_kernel<MP, true>;
-    hipLaunchKernelGGL(k, dim3(lpc_grid(k, ev.W, ev.n_big)), dim3(kBlock), 0, s, ev, M, mu, alpha, beta, ll,
+    hipLaunchKernelGGL(k, dim3(lpc_grid(k, ev.W, ev.n_big)), dim3(kLpcBlock), 0, s, ev, M, mu, alpha, beta, ll,
                        g_mu, g_alpha, g_beta, counter);
   } else {
     auto k = lpc_eval_kernel<MP, false>;
-    hipLaunchKernelGGL(k, dim3(lpc_grid(k, ev.W, ev.n_big)), dim3(kBlock), 0, s, ev, M, mu, alpha, beta, ll,
+    hipLaunchKernelGGL(k, dim3(lpc_grid(k, ev.W, ev.n_big)), dim3(kLpcBlock), 0, s, ev, M, mu, alpha, beta, ll,
                        g_mu, g_alpha, g_beta, counter);
   }
   return hipGetLastError();
@@ -1174,12 +1175,12 @@ hipError_t launch_lpc_fit(const Events& ev, int M, const FitParams& o, float* mu
     auto k = lpc_lbfgs_kernel<MP>;
     const int grid = (int)std::min<int64_t>(lpc_grid(k, ev.W, ev.n_big), ws_floats / block_ws<MP>());
     if (grid < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), 0, s, ev, M, o, mu, alpha, beta, ll, steps,
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kLpcBlock), 0, s, ev, M, o, mu, alpha, beta, ll, steps,
                        status, evals, ws, counter);
     return hipGetLastError();
   }
   auto k = lpc_fit_kernel<MP>;
-  hipLaunchKernelGGL(k, dim3(lpc_grid(k, ev.W, ev.n_big)), dim3(kBlock), 0, s, ev, M, o, mu, alpha, beta, ll,
+  hipLaunchKernelGGL(k, dim3(lpc_grid(k, ev.W, ev.n_big)), dim3(kLpcBlock), 0, s, ev, M, o, mu, alpha, beta, ll,
                      steps, status, evals, counter);
   return hipGetLastError();
 }
