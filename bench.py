@@ -310,9 +310,8 @@ def main() -> int:
         opts = mdhp.FitOptions(**opts_kw)
         if events is not None:
             events[0].record()
-        plan = mdhp.Plan(db.offsets, db.t, db.dim, db.T, b.M, mdhp.BETA_SHARED, device=dev)
-        if tuned != default_schedule:
-            plan.set_schedule(db.offsets, db.t, db.dim, db.T, tuned)
+        plan = mdhp.Plan(db.offsets, db.t, db.dim, db.T, b.M, mdhp.BETA_SHARED, device=dev,
+                         schedule=tuned)
         if warm:
             mu, al, be, used, _ = warmstart.warm_init(db, net, opts, plan)
         else:
@@ -365,9 +364,8 @@ def main() -> int:
     # The main pipeline (initial point + fit, on a prepared plan) eagerly and
     # as one captured HIP graph.
     from paper_2411_10258_amd import graph
-    plan = mdhp.Plan(db.offsets, db.t, db.dim, db.T, b.M, mdhp.BETA_SHARED, device=dev)
-    if tuned != default_schedule:
-        plan.set_schedule(db.offsets, db.t, db.dim, db.T, tuned)
+    plan = mdhp.Plan(db.offsets, db.t, db.dim, db.T, b.M, mdhp.BETA_SHARED, device=dev,
+                     schedule=tuned)
     gopts = mdhp.FitOptions(**main_kw)
     gnet = net if main_label.startswith("warm") else None
     gbatch = (db.offsets, db.t, db.dim, db.T)

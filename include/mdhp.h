@@ -239,6 +239,13 @@ mdhp_status mdhp_plan_set_schedule(mdhp_plan* plan, const mdhp_batch* batch, int
 /* The plan's current schedule value (0 for kind 0 or a NULL plan). */
 int32_t mdhp_plan_schedule(const mdhp_plan* plan);
 
+/* mdhp_plan_create with a schedule chosen beforehand (a candidate of the
+ * plan's kind, e.g. from an earlier mdhp_plan_autotune of the same batch
+ * shape; 0 = default), prepared once in that layout.  MDHP_E_INVAL for a
+ * value that is not a candidate. */
+mdhp_status mdhp_plan_create_scheduled(const mdhp_batch* batch, int32_t M, int32_t beta_mode,
+                                       int32_t schedule, void* stream, mdhp_plan** out);
+
 /* ------------------------------------------------------------------------
  * Learned warm start (an addition around the paper's solver, which fits
  * every window from scratch): count-histogram features, a 3-layer ReLU MLP

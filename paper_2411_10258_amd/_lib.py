@@ -23,7 +23,7 @@ EXPORTS = (
     "mdhp_surrogate_set_weights", "mdhp_surrogate_forward", "mdhp_surrogate_get_hidden",
     "mdhp_surrogate_backward", "mdhp_surrogate_get_gradients", "mdhp_surrogate_adam",
     "mdhp_surrogate_train_step", "mdhp_warm_start", "mdhp_cold_start", "mdhp_plan_autotune",
-    "mdhp_plan_set_schedule", "mdhp_plan_schedule",
+    "mdhp_plan_set_schedule", "mdhp_plan_schedule", "mdhp_plan_create_scheduled",
 )
 
 MDHP_OK = 0
@@ -92,6 +92,9 @@ def load() -> ctypes.CDLL:
     lib.mdhp_plan_autotune.argtypes = [P, ctypes.POINTER(MdhpBatch), ctypes.POINTER(MdhpFitOpts),
                                        I32, ctypes.POINTER(MdhpTuneResult), P]
     lib.mdhp_plan_set_schedule.argtypes = [P, ctypes.POINTER(MdhpBatch), I32, P]
+    lib.mdhp_plan_create_scheduled.argtypes = [ctypes.POINTER(MdhpBatch), I32, I32, I32, P,
+                                               ctypes.POINTER(P)]
+    lib.mdhp_plan_create_scheduled.restype = I32
     lib.mdhp_plan_schedule.argtypes = [P]
     lib.mdhp_plan_schedule.restype = I32
     lib.mdhp_features.argtypes = [ctypes.POINTER(MdhpBatch), I32, I32, P, P]

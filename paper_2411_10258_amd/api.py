@@ -78,13 +78,19 @@ def _batch(offsets, t, dim, T, device):
 
 
 def mdhp_plan_create(offsets, t, dim, T, M: int, beta_mode: int = BETA_SHARED,
-                     device="cuda", stream=None) -> int:
-    """Validates and prepares a batch; returns the raw plan handle."""
+                     device="cuda", stream=None, schedule: int = 0) -> int:
+    """Validates and prepares a batch; returns the raw plan handle.  schedule:
+    0 for the default, else a candidate schedule (mdhp_plan_create_scheduled)."""
     lib = _lib.load()
     _keep, b = _batch(offsets, t, dim, T, device)
     h = ctypes.c_void_p()
-    _lib.check(lib.mdhp_plan_create(ctypes.byref(b), int(M), int(beta_mode),
-                                    ctypes.c_void_p(_stream(stream)), ctypes.byref(h)))
+    if schedule:
+        _lib.check(lib.mdhp_plan_create_scheduled(ctypes.byref(b), int(M), int(beta_mode),
+                                                  int(schedule), ctypes.c_void_p(_stream(stream)),
+                                                  ctypes.byref(h)))
+    else:
+        _lib.check(lib.mdhp_plan_create(ctypes.byref(b), int(M), int(beta_mode),
+                                        ctypes.c_void_p(_stream(stream)), ctypes.byref(h)))
     return h.value
 
 
@@ -159,12 +165,12 @@ class Plan:
     """
 
     def __init__(self, offsets, t, dim, T, M: int, beta_mode: int = BETA_SHARED,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, schedule: int = 0):
         self.device = torch.device(device)
         self.M = int(M)
         self.beta_mode = int(beta_mode)
         self.handle = None
-        self.handle = mdhp_plan_create(offsets, t, dim, T, M, beta_mode, device, stream)
+        self.handle = mdhp_plan_create(offsets, t, dim, T, M, beta_mode, device, stream, schedule)
         lib = _lib.load()
         self.W = int(lib.mdhp_plan_windows(ctypes.c_void_p(self.handle)))
         self.n_events = int(lib.mdhp_plan_events(ctypes.c_void_p(self.handle)))

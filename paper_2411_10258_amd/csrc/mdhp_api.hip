@@ -356,6 +356,25 @@ mdhp_status mdhp_plan_create(const mdhp_batch* b, int32_t M, int32_t beta_mode, 
   return build_plan(b, M, beta_mode, kBigWindow, (hipStream_t)stream, out);
 }
 
+mdhp_status mdhp_plan_create_scheduled(const mdhp_batch* b, int32_t M, int32_t beta_mode,
+                                       int32_t schedule, void* stream, mdhp_plan** out) {
+  if (schedule == 0) return mdhp_plan_create(b, M, beta_mode, stream, out);
+  if (out) *out = nullptr;
+  const bool lane_major = beta_mode == MDHP_BETA_SHARED && M >= 1 && M <= kLaneMajorMaxM;
+  if (lane_major) {
+    const int32_t c[] = {512, 1024, 2048, 4096, MDHP_TEAM_NEVER};
+    bool known = false;
+    for (int32_t v : c) known = known || v == schedule;
+    if (!known) return fail(MDHP_E_INVAL, "plan_create: schedule is not a candidate");
+    return build_plan(b, M, beta_mode, schedule, (hipStream_t)stream, out);
+  }
+  if (beta_mode != MDHP_BETA_SHARED || !shared_scatter_ok(M, schedule))
+    return fail(MDHP_E_INVAL, "plan_create: schedule is not a candidate");
+  const mdhp_status st = build_plan(b, M, beta_mode, kBigWindow, (hipStream_t)stream, out);
+  if (st == MDHP_OK) (*out)->scatter = schedule;
+  return st;
+}
+
 void mdhp_plan_destroy(mdhp_plan* p) {
   if (!plan_ok(p)) return;
   (void)hipDeviceSynchronize();

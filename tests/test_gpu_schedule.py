@@ -62,6 +62,10 @@ def test_every_schedule_matches_oracle(gpu, oracle_lib, synth_lib, M, values, ti
         plan.set_schedule(b.offsets, b.t, b.dim, b.T, v)
         assert plan.schedule == v
         _check(gpu, oracle_lib, plan, b, th, f"M={M} schedule {v}")
+        fresh = gpu.Plan(b.offsets, b.t, b.dim, b.T, b.M, 0, schedule=v)  # prepared once
+        assert fresh.schedule == v
+        _check(gpu, oracle_lib, fresh, b, th, f"M={M} created with schedule {v}")
+        fresh.close()
     plan.close()
 
 
@@ -70,6 +74,8 @@ def test_schedule_rejects_bad_requests(gpu, synth_lib):
     plan = gpu.Plan(b.offsets, b.t, b.dim, b.T, b.M, 0)
     with pytest.raises(gpu.MdhpError, match="E_INVAL"):
         plan.set_schedule(b.offsets, b.t, b.dim, b.T, 777)
+    with pytest.raises(gpu.MdhpError, match="E_INVAL"):
+        gpu.Plan(b.offsets, b.t, b.dim, b.T, b.M, 0, schedule=777)
     other = synth_lib.random_small(4, 9, 16, 0, n_lo=10, n_hi=400)
     with pytest.raises(gpu.MdhpError, match="E_INVAL"):
         plan.set_schedule(other.offsets, other.t, other.dim, other.T, 2048)
