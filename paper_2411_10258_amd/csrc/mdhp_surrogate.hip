@@ -5,7 +5,8 @@
 // start wherever it has the higher likelihood.
 //
 // The paper fits every window from scratch; this component is a systems
-// addition around its solver (its fits remain the judge of the prediction).
+// addition around its solver (the solver's likelihood decides whether a
+// prediction is used).
 
 #include <cmath>
 #include <cstring>
