@@ -13,7 +13,7 @@ def _tensors(b):
     return tuple(torch.from_numpy(x).cuda() for x in (b.offsets, b.t, b.dim, b.T))
 
 
-def _replays(gpu, plan, opts, net=None, batch=None, exact=True, scale=None):
+def _replays(gpu, plan, opts, net=None, batch=None, exact=True, scale=None, tol=1e-5):
     import torch
     from paper_2411_10258_amd import graph
     extra = {}
@@ -34,7 +34,7 @@ def _replays(gpu, plan, opts, net=None, batch=None, exact=True, scale=None):
                 assert (a is None and e is None) or np.array_equal(a, e), f"replay {r}"
         else:
             gap = np.abs(out[3] - ref[3]) / scale
-            assert gap.max() <= 1e-5, f"replay {r}: ll differs by {gap.max():.3g}"
+            assert gap.max() <= tol, f"replay {r}: ll differs by {gap.max():.3g}"
 
 
 def test_graph_cold_lbfgs_m16(gpu, synth_lib):
@@ -60,16 +60,16 @@ def test_graph_warm_padam_m16(gpu, synth_lib):
     net.close()
 
 
-def test_graph_cold_lbfgs_wide(gpu, synth_lib):
+def test_graph_cold_pgd_wide(gpu, synth_lib):
     # M = 20: pass 1 and Gmu use LDS adds whose order varies from run to run,
-    # so two runs of the same fit may take different L-BFGS paths.  Run to
-    # convergence and compare ll at the fit tolerance's scale max(|ll|, N).
+    # so two runs differ by rounding.  A fixed number of projected gradient
+    # steps (no line search, no stop) keeps those differences at rounding
+    # level, so replays and the eager run agree to 1e-6 of max(|ll|, N).
     b = synth_lib.random_small(5, 16, 20, 0, n_lo=200, n_hi=3000)
-    print(f"[graph] cold L-BFGS M=20 W={b.W}", flush=True)
+    print(f"[graph] cold PGD M=20 W={b.W}", flush=True)
     plan = gpu.Plan(b.offsets, b.t, b.dim, b.T, b.M, 0)
-    opts = gpu.FitOptions(max_steps=500, optimizer=gpu.OPT_LBFGS, ll_tol=1e-7)
-    import torch
+    opts = gpu.FitOptions(max_steps=20, optimizer=gpu.OPT_PGD, lr=1e-2, ll_tol=0.0)
     from paper_2411_10258_amd import graph
     ll = graph.fit_pipeline(plan, opts)[3].cpu().numpy()
-    _replays(gpu, plan, opts, exact=False, scale=np.maximum(np.abs(ll), b.counts))
+    _replays(gpu, plan, opts, exact=False, scale=np.maximum(np.abs(ll), b.counts), tol=1e-6)
     plan.close()
