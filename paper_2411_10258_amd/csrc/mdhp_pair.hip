@@ -30,21 +30,27 @@ namespace mdhp {
 
 namespace {
 
+constexpr float kLog2e = 1.44269504088896340736f;
+
 template <int P>
 struct PairCfg {
   static constexpr int Q = P + 1;                      // padded stride
-  static constexpr int THREADS = P <= 16 ? 256 : 128;  // workgroup size
+  static constexpr int THREADS = 256;                  // workgroup size
   static constexpr int G = THREADS / P;                // chunks per window
   static constexpr int OWN = (P * P + THREADS - 1) / THREADS;
   static constexpr int B = P < 16 ? P : 16;            // events per loaded batch
+  static constexpr int WAVES = THREADS / 64;
 };
 
+// LDS of one workgroup.  At P = 32 the eight chunks' states and gradient
+// sums take 132 KB; the rest is kept small enough for the whole to fit in
+// one CU's 160 KB.
 template <int P>
 struct PairLds {
   using C = PairCfg<P>;
   static constexpr int Q = C::Q, G = C::G;
   float alpha[P * Q];  // [m * Q + n], zero outside M x M
-  float beta[P * Q];   // [m * Q + n], one outside M x M
+  float nbeta[P * Q];  // -beta_mn log2(e), the exponent scale of exp2 (beta one outside M x M)
   float mu[P];
   float Rs[G][P * Q];  // chunk state, column-major [n * Q + m]
   float Ss[G][P * Q];
@@ -53,44 +59,173 @@ struct PairLds {
   float cnt[G][P];     // events per source dimension in the chunk
   float cD[G];
   int cF[G];
-  float gR[P * Q];  // FP32 sums of R_mn / lambda over target-m events, [m * Q + n]
-  float gS[P * Q];  // same for S_mn
-  double Cmn[P * P];  // (N_n - E_mn) / beta_mn, [m * P + n]
-  double Fmn[P * P];  // F_mn = sum_{k: d_k = n} (T - t_k) e^{-beta_mn (T - t_k)}
-  double red[2][C::THREADS];
+  float gR[G][P * Q];  // per chunk, FP32 sums of R_mn / lambda over target-m events, [m * Q + n]
+  float gS[G][P * Q];  // same for S_mn
+  float red[2][C::THREADS];  // per-lane sums of a chunk: log2 lambda, 1/lambda
   double gmu[P];
+  double wsum[C::WAVES];
   double scal[2];
   int next_window;
   int stop;
 };
 
+// The pairs a thread owns, e = tid + k THREADS < P^2 (m = e / P, n = e % P),
+// with their exact decay and compensator sums in registers.
 template <int P>
-__device__ __forceinline__ void column_update(PairLds<P>& sh, float* Rs, float* Ss, int lane,
-                                              int d, float& z, float& cn) {
-  constexpr int Q = PairCfg<P>::Q;
-  const float zd = __shfl(z, d, P);
-  const int a = d * Q + lane;
-  const float Rt = Rs[a];
-  const float St = Ss[a];
-  if (zd > 0.f) {
-    const float e = __expf(-sh.beta[lane * Q + d] * zd);
-    Rs[a] = fmaf(e, Rt, 1.f);
-    Ss[a] = e * fmaf(zd, Rt, St);
+struct PairOwn {
+  static constexpr int OWN = PairCfg<P>::OWN;
+  float beta[OWN];   // beta_mn (one outside M x M)
+  double C[OWN];     // (N_n - E_mn) / beta_mn
+  double F[OWN];     // F_mn = sum_{k: d_k = n} (T - t_k) e^{-beta_mn (T - t_k)}
+};
+
+// Event J of the loaded batch, to every lane of the group.  At P = 32 the
+// batch is held once per 16-lane row of the group, so a row broadcast does.
+template <int P, int J>
+__device__ __forceinline__ float batch_bcast(float x) {
+  if constexpr (P == 32)
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x),
+                                                              0x150 + J, 0xF, 0xF, false));
+  else
+    return group_bcast<P, J>(x);
+}
+
+// v of lane src of the caller's group (src uniform within the group).  At
+// P = 32 (two groups per wavefront) by lane reads into scalars; narrower
+// groups by a permute.
+template <int P>
+__device__ __forceinline__ float group_lane(float v, int src) {
+  if constexpr (P == 32) {
+    const int vi = __builtin_bit_cast(int, v);
+    const int s0 = __builtin_amdgcn_readlane(src, 0);
+    const int s1 = __builtin_amdgcn_readlane(src, 32) + 32;
+    const int a = __builtin_amdgcn_readlane(vi, s0);
+    const int b = __builtin_amdgcn_readlane(vi, s1);
+    return __builtin_bit_cast(float, (threadIdx.x & 32) ? b : a);
   } else {
-    Rs[a] = Rt + 1.f;
-  }
-  if (lane == d) {
-    cn = zd > 0.f ? 1.f : cn + 1.f;
-    z = 0.f;
+    return __shfl(v, src, P);
   }
 }
 
-// Evaluates one window with parameters in LDS.  Results: sh.scal[0] = ll;
-// if GRAD also sh.gR / sh.gS (FP32 sums), sh.Cmn, sh.Fmn, sh.gmu.
+// Sum over the P lanes of the group; at P = 32 the last step (the other
+// 16-lane row) is a lane swap instead of a permute through LDS.
+template <int P>
+__device__ __forceinline__ float pair_group_sum(float v) {
+  if constexpr (P == 32) {
+    v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);  // row_half_mirror
+    v += dpp<0x140>(v);  // row_mirror
+    const unsigned u = __builtin_bit_cast(unsigned, v);
+    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    const unsigned x = r[0], y = r[1];  // row 2k's and row 2k+1's totals in every lane
+    return __uint_as_float(x) + __uint_as_float(y);
+  } else {
+    return group_sum<P>(v);
+  }
+}
+
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// One event of a chunk as a lane sees it: the dimension d, the lane's
+// elapsed time z and pending count c before the event (row read), the
+// elapsed time zd of column d (column update) and the LDS values both read.
+struct PairEvent {
+  int d, ac;        // ac = d * Q + lane: column d's entry for target lane, also (d, lane) of alpha/beta
+  float z, c, zd, inc, ok;
+  float Rrow, Srow, brow, arow, mud;  // row read: column lane, target d
+  float Rcol, Scol, bcol;             // column update: column d, target lane
+};
+
+// Advances the lane's lazy clock to event J of the batch and issues every
+// LDS read the event needs.  Events past the chunk's end (J >= nv) are null:
+// no elapsed time, no count, no contribution.
+template <int P, int J>
+__device__ __forceinline__ PairEvent pair_issue(PairLds<P>& sh, const float* Rs, const float* Ss,
+                                                int lane, float dt_l, int d_l, int nv, float& z,
+                                                float& cn) {
+  constexpr int Q = PairCfg<P>::Q;
+  PairEvent e;
+  const int d = __builtin_bit_cast(int, batch_bcast<P, J>(__builtin_bit_cast(float, d_l)));
+  const int ar = lane * Q + d;
+  e.d = d;
+  e.ac = d * Q + lane;
+  e.Rcol = Rs[e.ac];
+  e.Scol = Ss[e.ac];
+  e.bcol = sh.nbeta[ar];
+  e.Rrow = Rs[ar];
+  e.Srow = Ss[ar];
+  e.brow = sh.nbeta[e.ac];
+  e.arow = sh.alpha[e.ac];
+  e.mud = sh.mu[d];
+  // The reads above stay ahead of the previous event's remaining work.
+  __builtin_amdgcn_sched_barrier(0);
+  const float dt = batch_bcast<P, J>(dt_l);
+  const bool ok = J < nv;
+  z += dt;
+  const float zd = group_lane<P>(z, d);
+  e.z = z;
+  e.c = cn;
+  e.zd = ok ? zd : 0.f;
+  e.inc = ok ? 1.f : 0.f;
+  e.ok = e.inc;
+  // The lane's own column restarts its clock (arithmetic, not a branch).
+  const float own = (ok && lane == d) ? 1.f : 0.f;
+  const float ncn = zd > 0.f ? 1.f : cn + 1.f;
+  cn = fmaf(own, ncn - cn, cn);
+  z = fmaf(-own, z, z);
+  return e;
+}
+
+// Column update of source d for target lane: the column decays to the
+// event's time and gains the event (a null event writes the same values).
+__device__ __forceinline__ void pair_column(float* Rs, float* Ss, const PairEvent& e) {
+  const float ec = exp2_fast(e.bcol * e.zd);
+  Rs[e.ac] = fmaf(ec, e.Rcol, e.inc);
+  Ss[e.ac] = ec * fmaf(e.zd, e.Rcol, e.Scol);
+}
+
+// Row read for target d (lane = source n): the lane's term of the intensity,
+// log2 lambda on lane 0, and with GRAD the gradient sums R/lambda, S/lambda.
 template <int P, bool GRAD>
-__device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, const float* __restrict__ dtg,
-                                 const uint8_t* __restrict__ dg, int64_t begin, int n, double T,
-                                 float end_gap, int M) {
+__device__ __forceinline__ void pair_row(PairLds<P>& sh, const PairEvent& e, int lane, int grp,
+                                         float& llp, float& gmup) {
+  // The chunk's own gradient sums: a plain read-modify-write (LDS float
+  // atomics are several times slower), read early, written last.
+  float oR = 0.f, oS = 0.f;
+  if constexpr (GRAD) {
+    oR = sh.gR[grp][e.ac];
+    oS = sh.gS[grp][e.ac];
+  }
+  const float ex = exp2_fast(e.brow * e.z);
+  const float R = ex * e.Rrow - (e.z == 0.f ? e.c : 0.f);
+  const float S = ex * fmaf(e.z, e.Rrow, e.Srow);
+  const float lam = pair_group_sum<P>(e.arow * R) + e.mud;
+  const bool ok = e.ok != 0.f;
+  llp += (ok && lane == 0) ? __builtin_amdgcn_logf(lam) : 0.f;
+  if constexpr (GRAD) {
+    const float w = ok ? __builtin_amdgcn_rcpf(lam) : 0.f;
+    sh.gR[grp][e.ac] = fmaf(w, R, oR);
+    sh.gS[grp][e.ac] = fmaf(w, S, oS);
+    gmup += lane == e.d ? w : 0.f;
+  }
+}
+
+// Evaluates one window with parameters in LDS (and the owned decays in
+// own.beta).  Results: sh.scal[0] = ll, own.C and own.F; if GRAD also sh.gR /
+// sh.gS (FP32 sums) and sh.gmu.
+//
+// Within a chunk the events are a chain through LDS (an event's row read
+// sees every earlier column update), so per event the reads go out together
+// and the column update is written before the next event's reads; the
+// event's intensity, logarithm and gradient sums follow the next event's
+// reads, off the chain.  The gradient sums are kept per chunk, so that the
+// chunks never write the same LDS word.
+template <int P, bool GRAD>
+__device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, PairOwn<P>& own,
+                                                 const float* __restrict__ dtg,
+                                                 const uint8_t* __restrict__ dg, int64_t begin,
+                                                 int n, double T, float end_gap, int M) {
   using C = PairCfg<P>;
   constexpr int Q = C::Q, G = C::G, B = C::B;
   const int tid = threadIdx.x;
@@ -103,7 +238,12 @@ __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, const float* __
   const int c = (n + G - 1) / G;
   const int j0 = min(grp * c, n);
   const int len = min(j0 + c, n) - j0;
-  const int nb = (len + B - 1) / B;  // uniform within a group
+  const int nb = (c + B - 1) / B;  // uniform over the workgroup; short chunks run null events
+  auto load = [&](int bb, float& dt_l, int& d_l) {
+    const int jl = bb * B + (lane & (B - 1));
+    dt_l = jl < len ? dtw[j0 + jl] : 0.f;
+    d_l = jl < len ? (int)dw[j0 + jl] : 0;
+  };
 
   // Pass 1: zero-start state of this chunk, column updates only.
   for (int e = lane; e < P * Q; e += P) {
@@ -111,27 +251,42 @@ __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, const float* __
     Ss[e] = 0.f;
   }
   float z = 0.f, cn = 0.f, count = 0.f, delta = 0.f;
-  for (int bb = 0; bb < nb; ++bb) {
-    const int jl = bb * B + (lane & (B - 1));
-    const float dt_l = jl < len ? dtw[j0 + jl] : 0.f;
-    const float d_l = __builtin_bit_cast(float, jl < len ? (int)dw[j0 + jl] : 0);
-    const int nv = min(B, len - bb * B);
-    static_for<B>([&](auto J) {
-      constexpr int j = decltype(J)::value;
-      if (j < nv) {
-        const float dt = group_bcast<P, j>(dt_l);
-        const int d = __builtin_bit_cast(int, group_bcast<P, j>(d_l));
+  {
+    float dt_l, dt_n = 0.f;
+    int d_l, d_n = 0;
+    load(0, dt_l, d_l);
+    for (int bb = 0; bb < nb; ++bb) {
+      if (bb + 1 < nb) load(bb + 1, dt_n, d_n);
+      const int nv = len - bb * B;
+      static_for<B>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        const int d = __builtin_bit_cast(int, batch_bcast<P, j>(__builtin_bit_cast(float, d_l)));
+        const int a = d * Q + lane;
+        const float Rt = Rs[a], St = Ss[a], bc = sh.nbeta[lane * Q + d];
+        __builtin_amdgcn_sched_barrier(0);  // reads first, the clock work under their latency
+        const float dt = batch_bcast<P, j>(dt_l);
+        const bool ok = j < nv;
         z += dt;
         delta += dt;
-        count += lane == d ? 1.f : 0.f;
-        column_update<P>(sh, Rs, Ss, lane, d, z, cn);
-      }
-    });
+        const float zd0 = group_lane<P>(z, d);
+        const float zd = ok ? zd0 : 0.f;
+        const float own = (ok && lane == d) ? 1.f : 0.f;
+        count += own;
+        const float ncn = zd > 0.f ? 1.f : cn + 1.f;
+        cn = fmaf(own, ncn - cn, cn);
+        z = fmaf(-own, z, z);
+        const float ec = exp2_fast(bc * zd);
+        Rs[a] = fmaf(ec, Rt, ok ? 1.f : 0.f);
+        Ss[a] = ec * fmaf(zd, Rt, St);
+      });
+      dt_l = dt_n;
+      d_l = d_n;
+    }
   }
   // Lazy columns -> full state at the chunk's last event (lane = column n).
   for (int m = 0; m < P; ++m) {
     const int a = lane * Q + m;
-    const float e = __expf(-sh.beta[m * Q + lane] * z);
+    const float e = exp2_fast(sh.nbeta[m * Q + lane] * z);
     const float Rt = Rs[a];
     Rs[a] = e * Rt - (z == 0.f ? cn : 0.f);
     Ss[a] = e * fmaf(z, Rt, Ss[a]);
@@ -146,10 +301,13 @@ __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, const float* __
   // Ordered combine over chunks, one pair (m, n) per thread slot; chunk g's
   // slot is overwritten with its start state.  The end state gives the
   // compensator sums E_mn, F_mn.
-  for (int e = tid; e < P * P; e += C::THREADS) {
+#pragma unroll
+  for (int k = 0; k < C::OWN; ++k) {
+    const int e = tid + k * C::THREADS;
+    if (e >= P * P) break;
     const int m = e / P, nn = e % P;
     const int a = nn * Q + m;
-    const float b = sh.beta[m * Q + nn];
+    const float b = own.beta[k];
     float R = 0.f, S = 0.f, Pc = 0.f, Ntot = 0.f;
     for (int g = 0; g < G; ++g) {
       const float Rl = sh.Rs[g][a], Sl = sh.Ss[g][a], Pg = sh.Pl[g][nn];
@@ -173,8 +331,8 @@ __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, const float* __
     const double E = ad * ((double)R + (double)Pc);
     const double F = ad * (double)S + gap * E;
     const bool in = m < M && nn < M;
-    sh.Cmn[m * P + nn] = in ? ((double)Ntot - E) / bd : 0.0;
-    sh.Fmn[m * P + nn] = in ? F : 0.0;
+    own.C[k] = in ? ((double)Ntot - E) / bd : 0.0;
+    own.F[k] = in ? F : 0.0;
   }
   __syncthreads();
   // Pass 2: from the exact chunk start, row reads (intensity, gradient
@@ -184,75 +342,80 @@ __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, const float* __
     for (int m = 0; m < P; ++m) Rs[lane * Q + m] += pend;  // pending events enter at weight 1
     z = 0.f;
     cn = pend;
-    float llp = 0.f, gmup = 0.f;
+    float llp = 0.f, gmup = 0.f;  // llp: sum of log2 lambda
+    float dt_l, dt_n = 0.f;
+    int d_l, d_n = 0;
+    load(0, dt_l, d_l);
     for (int bb = 0; bb < nb; ++bb) {
-      const int jl = bb * B + (lane & (B - 1));
-      const float dt_l = jl < len ? dtw[j0 + jl] : 0.f;
-      const float d_l = __builtin_bit_cast(float, jl < len ? (int)dw[j0 + jl] : 0);
-      const int nv = min(B, len - bb * B);
+      if (bb + 1 < nb) load(bb + 1, dt_n, d_n);
+      const int nv = len - bb * B;
+      PairEvent cur = pair_issue<P, 0>(sh, Rs, Ss, lane, dt_l, d_l, nv, z, cn);
       static_for<B>([&](auto J) {
         constexpr int j = decltype(J)::value;
-        if (j < nv) {
-          const float dt = group_bcast<P, j>(dt_l);
-          const int d = __builtin_bit_cast(int, group_bcast<P, j>(d_l));
-          z += dt;
-          // Row read for target d (lane = source n).
-          const int a = lane * Q + d;
-          const float Rt = Rs[a];
-          const float St = Ss[a];
-          const float e = __expf(-sh.beta[d * Q + lane] * z);
-          const float R = e * Rt - (z == 0.f ? cn : 0.f);
-          const float S = e * fmaf(z, Rt, St);
-          const float al = sh.alpha[d * Q + lane];
-          const float lam = group_sum<P>(al * R) + sh.mu[d];
-          llp += lane == 0 ? __logf(lam) : 0.f;
-          if constexpr (GRAD) {
-            const float w = __builtin_amdgcn_rcpf(lam);
-            atomicAdd(&sh.gR[d * Q + lane], w * R);
-            atomicAdd(&sh.gS[d * Q + lane], w * S);
-            gmup += lane == d ? w : 0.f;
-          }
-          column_update<P>(sh, Rs, Ss, lane, d, z, cn);
+        pair_column(Rs, Ss, cur);
+        if constexpr (j + 1 < B) {
+          const PairEvent nxt = pair_issue<P, j + 1>(sh, Rs, Ss, lane, dt_l, d_l, nv, z, cn);
+          pair_row<P, GRAD>(sh, cur, lane, grp, llp, gmup);
+          cur = nxt;
+        } else {
+          pair_row<P, GRAD>(sh, cur, lane, grp, llp, gmup);
         }
       });
+      dt_l = dt_n;
+      d_l = d_n;
     }
-    sh.red[0][tid] = (double)llp;
-    sh.red[1][tid] = (double)gmup;
+    sh.red[0][tid] = llp;
+    sh.red[1][tid] = gmup;
   }
+  // ll = sum log lambda - T sum mu - sum alpha_mn C_mn: the last sum over the
+  // owned pairs and the waves, the others over the chunks, then the lanes.
+  double p3 = 0.0;
+#pragma unroll
+  for (int k = 0; k < C::OWN; ++k) {
+    const int e = tid + k * C::THREADS;
+    if (e < P * P) p3 += (double)sh.alpha[(e / P) * Q + e % P] * own.C[k];
+  }
+  p3 = wave_sum(p3);
+  if ((tid & 63) == 0) sh.wsum[tid >> 6] = p3;
   __syncthreads();
-  if (tid < P) {
-    double l = 0.0, gm = 0.0;
-    for (int g = 0; g < G; ++g) {
-      l += sh.red[0][g * P + tid];
-      gm += sh.red[1][g * P + tid];
+  double l2 = 0.0, smu = 0.0;
+  if (tid < 64) {  // the first wavefront, whole
+    if (tid < P) {
+      double gm = 0.0;
+      for (int g = 0; g < G; ++g) {
+        l2 += (double)sh.red[0][g * P + tid];
+        gm += (double)sh.red[1][g * P + tid];
+      }
+      sh.gmu[tid] = tid < M ? gm - T : 0.0;
+      smu = tid < M ? (double)sh.mu[tid] : 0.0;
     }
-    sh.gmu[tid] = tid < M ? gm - T : 0.0;
-    sh.red[0][tid] = l;
-    sh.red[1][tid] = tid < M ? (double)sh.mu[tid] : 0.0;
+    l2 = wave_sum(l2);
+    smu = wave_sum(smu);
   }
-  __syncthreads();
   if (tid == 0) {
-    double p1 = 0.0, smu = 0.0, p3 = 0.0;
-    for (int k = 0; k < P; ++k) {
-      p1 += sh.red[0][k];
-      smu += sh.red[1][k];
-    }
-    for (int e = 0; e < P * P; ++e) p3 += (double)sh.alpha[(e / P) * Q + e % P] * sh.Cmn[e];
-    sh.scal[0] = p1 - T * smu - p3;
+    double s3 = 0.0;
+    for (int v = 0; v < C::WAVES; ++v) s3 += sh.wsum[v];
+    sh.scal[0] = l2 * 0.69314718055994530942 - T * smu - s3;  // log2 -> natural log
   }
   __syncthreads();
 }
 
 template <int P>
-__device__ void load_params_pair(PairLds<P>& sh, const float* __restrict__ mu,
+__device__ void load_params_pair(PairLds<P>& sh, PairOwn<P>& own, const float* __restrict__ mu,
                                  const float* __restrict__ alpha, const float* __restrict__ beta,
                                  int64_t w, int M) {
-  constexpr int Q = PairCfg<P>::Q;
-  for (int e = threadIdx.x; e < P * P; e += PairCfg<P>::THREADS) {
+  using C = PairCfg<P>;
+  constexpr int Q = C::Q;
+#pragma unroll
+  for (int k = 0; k < C::OWN; ++k) {
+    const int e = threadIdx.x + k * C::THREADS;
+    if (e >= P * P) break;
     const int m = e / P, n = e % P;
     const bool in = m < M && n < M;
     sh.alpha[m * Q + n] = in ? alpha[(w * M + m) * M + n] : 0.f;
-    sh.beta[m * Q + n] = in ? beta[(w * M + m) * M + n] : 1.f;
+    const float b = in ? beta[(w * M + m) * M + n] : 1.f;
+    own.beta[k] = b;
+    sh.nbeta[m * Q + n] = -b * kLog2e;
   }
   if (threadIdx.x < P) sh.mu[threadIdx.x] = threadIdx.x < M ? mu[w * M + threadIdx.x] : 0.f;
   __syncthreads();
@@ -269,9 +432,23 @@ __device__ int next_window_pair(PairLds<P>& sh, int* counter, int first) {
 
 template <int P>
 __device__ void zero_pair_accumulators(PairLds<P>& sh) {
-  for (int e = threadIdx.x; e < P * PairCfg<P>::Q; e += PairCfg<P>::THREADS) {
-    sh.gR[e] = 0.f;
-    sh.gS[e] = 0.f;
+  for (int e = threadIdx.x; e < PairCfg<P>::G * P * PairCfg<P>::Q; e += PairCfg<P>::THREADS) {
+    sh.gR[0][e] = 0.f;
+    sh.gS[0][e] = 0.f;
+  }
+}
+
+// Sum over the chunks of the gradient sums of pair (m, n), which it clears
+// for the next evaluation.
+template <int P>
+__device__ __forceinline__ void take_pair_sums(PairLds<P>& sh, int a, double& gR, double& gS) {
+  gR = 0.0;
+  gS = 0.0;
+  for (int g = 0; g < PairCfg<P>::G; ++g) {
+    gR += (double)sh.gR[g][a];
+    gS += (double)sh.gS[g][a];
+    sh.gR[g][a] = 0.f;
+    sh.gS[g][a] = 0.f;
   }
 }
 
@@ -280,27 +457,30 @@ __global__ __launch_bounds__(PairCfg<P>::THREADS) void pair_eval_kernel(
     Events ev, int M, const float* mu, const float* alpha, const float* beta, double* ll,
     float* g_mu, float* g_alpha, float* g_beta, int* counter) {
   __shared__ PairLds<P> sh;
-  constexpr int Q = PairCfg<P>::Q;
+  using C = PairCfg<P>;
+  constexpr int Q = C::Q;
   const int tid = threadIdx.x;
+  PairOwn<P> own;
   zero_pair_accumulators(sh);
   for (int q = next_window_pair(sh, counter, 1); q < ev.W; q = next_window_pair(sh, counter, 0)) {
     const int64_t w = ev.order[q];
-    load_params_pair(sh, mu, alpha, beta, w, M);
+    load_params_pair(sh, own, mu, alpha, beta, w, M);
     const double T = ev.T[w];
-    eval_window_pair<P, GRAD>(sh, ev.dt, ev.d, ev.begin[w], ev.n[w], T, ev.end_gap[w], M);
+    eval_window_pair<P, GRAD>(sh, own, ev.dt, ev.d, ev.begin[w], ev.n[w], T, ev.end_gap[w], M);
     if (tid == 0) ll[w] = sh.scal[0];
     if constexpr (GRAD) {
       if (tid < M) g_mu[w * M + tid] = (float)sh.gmu[tid];
-      for (int e = tid; e < P * P; e += PairCfg<P>::THREADS) {
+#pragma unroll
+      for (int k = 0; k < C::OWN; ++k) {
+        const int e = tid + k * C::THREADS;
+        if (e >= P * P) break;
         const int m = e / P, n = e % P;
-        const double C = sh.Cmn[e], F = sh.Fmn[e];
-        const double gR = (double)sh.gR[m * Q + n], gS = (double)sh.gS[m * Q + n];
-        sh.gR[m * Q + n] = 0.f;
-        sh.gS[m * Q + n] = 0.f;
+        double gR, gS;
+        take_pair_sums(sh, m * Q + n, gR, gS);
         if (m < M && n < M) {
-          const double a = (double)sh.alpha[m * Q + n], b = (double)sh.beta[m * Q + n];
-          g_alpha[(w * M + m) * M + n] = (float)(gR - C);
-          g_beta[(w * M + m) * M + n] = (float)(-a * (gS + (F - C) / b));
+          const double a = (double)sh.alpha[m * Q + n], b = (double)own.beta[k];
+          g_alpha[(w * M + m) * M + n] = (float)(gR - own.C[k]);
+          g_beta[(w * M + m) * M + n] = (float)(-a * (gS + (own.F[k] - own.C[k]) / b));
         }
       }
     }
@@ -316,11 +496,12 @@ __global__ __launch_bounds__(PairCfg<P>::THREADS) void pair_fit_kernel(
   using C = PairCfg<P>;
   constexpr int Q = C::Q, OWN = C::OWN;
   const int tid = threadIdx.x;
+  PairOwn<P> own;
   float m1a[OWN], m2a[OWN], m1b[OWN], m2b[OWN];
   zero_pair_accumulators(sh);
   for (int q = next_window_pair(sh, counter, 1); q < ev.W; q = next_window_pair(sh, counter, 0)) {
     const int64_t w = ev.order[q];
-    load_params_pair(sh, mu, alpha, beta, w, M);
+    load_params_pair(sh, own, mu, alpha, beta, w, M);
     const int n = ev.n[w];
     const double T = ev.T[w];
     const double rate = (double)max(n, 1) / T;
@@ -333,7 +514,7 @@ __global__ __launch_bounds__(PairCfg<P>::THREADS) void pair_fit_kernel(
     double ll_prev = 0.0, b1t = 1.0, b2t = 1.0;
     int s = 0, st = MDHP_FIT_MAX_STEPS;
     for (s = 0;; ++s) {
-      eval_window_pair<P, true>(sh, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], M);
+      eval_window_pair<P, true>(sh, own, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], M);
       const double l = sh.scal[0];
       // Gradient of the owned pairs (and reset of the FP32 sums).
       double ga[OWN], gb[OWN];
@@ -344,13 +525,11 @@ __global__ __launch_bounds__(PairCfg<P>::THREADS) void pair_fit_kernel(
         ga[k] = gb[k] = 0.0;
         if (e < P * P) {
           const int m = e / P, nn = e % P;
-          const double Cv = sh.Cmn[e], F = sh.Fmn[e];
-          const double gR = (double)sh.gR[m * Q + nn], gS = (double)sh.gS[m * Q + nn];
-          sh.gR[m * Q + nn] = 0.f;
-          sh.gS[m * Q + nn] = 0.f;
-          const double a = (double)sh.alpha[m * Q + nn], b = (double)sh.beta[m * Q + nn];
-          ga[k] = gR - Cv;
-          gb[k] = -a * (gS + (F - Cv) / b);
+          double gR, gS;
+          take_pair_sums(sh, m * Q + nn, gR, gS);
+          const double a = (double)sh.alpha[m * Q + nn], b = (double)own.beta[k];
+          ga[k] = gR - own.C[k];
+          gb[k] = -a * (gS + (own.F[k] - own.C[k]) / b);
           if (!isfinite(ga[k]) || !isfinite(gb[k])) bad = true;
         }
       }
@@ -386,19 +565,18 @@ __global__ __launch_bounds__(PairCfg<P>::THREADS) void pair_fit_kernel(
       };
       // alpha, beta of the owned pairs and mu; the new values are written
       // after everyone has read the old ones for the gradient above.
-      float na[OWN], nbv[OWN];
+      float na[OWN];
 #pragma unroll
       for (int k = 0; k < OWN; ++k) {
         const int e = tid + k * C::THREADS;
-        na[k] = nbv[k] = 0.f;
+        na[k] = 0.f;
         if (e < P * P) {
           const int m = e / P, nn = e % P;
           if (m < M && nn < M) {
             na[k] = (float)fmax((double)sh.alpha[m * Q + nn] + step(ga[k], m1a[k], m2a[k]), 0.0);
-            nbv[k] = o.fix_beta ? sh.beta[m * Q + nn]
-                                : (float)fmax((double)sh.beta[m * Q + nn] +
-                                                  step(gb[k], m1b[k], m2b[k]),
-                                              beta_min);
+            if (!o.fix_beta)
+              own.beta[k] = (float)fmax((double)own.beta[k] + step(gb[k], m1b[k], m2b[k]),
+                                        beta_min);
           }
         }
       }
@@ -412,7 +590,7 @@ __global__ __launch_bounds__(PairCfg<P>::THREADS) void pair_fit_kernel(
           const int m = e / P, nn = e % P;
           if (m < M && nn < M) {
             sh.alpha[m * Q + nn] = na[k];
-            sh.beta[m * Q + nn] = nbv[k];
+            sh.nbeta[m * Q + nn] = -own.beta[k] * kLog2e;
           }
         }
       }
@@ -422,14 +600,20 @@ __global__ __launch_bounds__(PairCfg<P>::THREADS) void pair_fit_kernel(
     // The FP32 sums of the last evaluation are still in LDS when the loop
     // stops before reading them; clear them for the next window.
     __syncthreads();
-    for (int e = tid; e < P * Q; e += C::THREADS) {
-      sh.gR[e] = 0.f;
-      sh.gS[e] = 0.f;
+    for (int e = tid; e < C::G * P * Q; e += C::THREADS) {
+      sh.gR[0][e] = 0.f;
+      sh.gS[0][e] = 0.f;
     }
-    for (int e = tid; e < M * M; e += C::THREADS) {
-      const int m = e / M, nn = e % M;
-      alpha[w * M * M + e] = sh.alpha[m * Q + nn];
-      beta[w * M * M + e] = sh.beta[m * Q + nn];
+#pragma unroll
+    for (int k = 0; k < OWN; ++k) {
+      const int e = tid + k * C::THREADS;
+      if (e < P * P) {
+        const int m = e / P, nn = e % P;
+        if (m < M && nn < M) {
+          alpha[(w * M + m) * M + nn] = sh.alpha[m * Q + nn];
+          beta[(w * M + m) * M + nn] = own.beta[k];
+        }
+      }
     }
     if (tid < M) mu[w * M + tid] = sh.mu[tid];
     if (tid == 0) {
