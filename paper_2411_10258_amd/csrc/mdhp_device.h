@@ -59,15 +59,33 @@ __device__ __forceinline__ double wave_max(double v) {
   return fmax(fmax(lane64(v, 0), lane64(v, 16)), fmax(lane64(v, 32), lane64(v, 48)));
 }
 
+// v of rows 2k and 2k+1 (16 lanes each) added, in every lane of both rows
+// (a lane swap between the two rows).
+__device__ __forceinline__ float rows_pair_sum(float v) {
+  const unsigned u = __builtin_bit_cast(unsigned, v);
+  const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  const unsigned x = r[0], y = r[1];  // (a bit cast of r[i] itself reads element 0)
+  return __uint_as_float(x) + __uint_as_float(y);
+}
+
+// v of the two 32-lane halves of the wavefront added, in every lane.
+__device__ __forceinline__ float halves_sum(float v) {
+  const unsigned u = __builtin_bit_cast(unsigned, v);
+  const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  const unsigned x = r[0], y = r[1];
+  return __uint_as_float(x) + __uint_as_float(y);
+}
+
 // Sum over the P consecutive lanes of a group; every lane gets the sum.
+// Lane swaps across rows and halves: no LDS traffic.
 template <int P>
 __device__ __forceinline__ float group_sum(float v) {
   if constexpr (P >= 2) v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
   if constexpr (P >= 4) v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
   if constexpr (P >= 8) v += dpp<0x141>(v);  // row_half_mirror: the other quad of the 8
   if constexpr (P >= 16) v += dpp<0x140>(v); // row_mirror: the other 8 of the 16-lane row
-  if constexpr (P >= 32) v += __shfl_xor(v, 16);
-  if constexpr (P >= 64) v += __shfl_xor(v, 32);
+  if constexpr (P >= 32) v = rows_pair_sum(v);
+  if constexpr (P >= 64) v = halves_sum(v);
   return v;
 }
 
@@ -103,9 +121,16 @@ __device__ __forceinline__ float row_shr(float v) {
                                                                 0x110 + K, 0xF, 0xF, true));
 }
 
+// v from lane - 1 of the wavefront, 0 in lane 0 (DPP wave_shr:1 with
+// bound_ctrl).
+__device__ __forceinline__ float wave_shr1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                0x138, 0xF, 0xF, true));
+}
+
 // Inclusive prefix sum over the P lanes of a group (lane order).  Within
 // 16-lane rows by DPP shifts; groups wider than a row add the earlier rows'
-// totals read across lanes.
+// totals, read from the rows' last lanes as scalars.
 template <int P>
 __device__ __forceinline__ float group_scan(float v, int lane) {
   constexpr int R = P < 16 ? P : 16;
@@ -127,13 +152,18 @@ __device__ __forceinline__ float group_scan(float v, int lane) {
   }
   if constexpr (P > 16) {
     // Add the totals of the earlier 16-lane rows of the group.
+    static_assert(P == 32 || P == 64, "");
     const int row = lane >> 4;
-    const float t0 = __shfl(v, (threadIdx.x & ~(P - 1) & 63) + 15, 64);
-    float add = row >= 1 ? t0 : 0.f;
-    if constexpr (P > 32) {
-      const float t1 = __shfl(v, (threadIdx.x & ~(P - 1) & 63) + 31, 64);
-      const float t2 = __shfl(v, (threadIdx.x & ~(P - 1) & 63) + 47, 64);
-      add += (row >= 2 ? t1 : 0.f) + (row >= 3 ? t2 : 0.f);
+    const int vi = __builtin_bit_cast(int, v);
+    const float r15 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(vi, 15));
+    const float r47 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(vi, 47));
+    float add;
+    if constexpr (P == 32) {
+      add = row >= 1 ? ((threadIdx.x & 32) ? r47 : r15) : 0.f;
+    } else {
+      const float r31 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(vi, 31));
+      add = row >= 1 ? r15 : 0.f;
+      add += (row >= 2 ? r31 : 0.f) + (row >= 3 ? r47 : 0.f);
     }
     v += add;
   }

@@ -107,24 +107,6 @@ __device__ __forceinline__ float group_lane(float v, int src) {
   }
 }
 
-// Sum over the P lanes of the group; at P = 32 the last step (the other
-// 16-lane row) is a lane swap instead of a permute through LDS.
-template <int P>
-__device__ __forceinline__ float pair_group_sum(float v) {
-  if constexpr (P == 32) {
-    v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp<0x141>(v);  // row_half_mirror
-    v += dpp<0x140>(v);  // row_mirror
-    const unsigned u = __builtin_bit_cast(unsigned, v);
-    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
-    const unsigned x = r[0], y = r[1];  // row 2k's and row 2k+1's totals in every lane
-    return __uint_as_float(x) + __uint_as_float(y);
-  } else {
-    return group_sum<P>(v);
-  }
-}
-
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // One event of a chunk as a lane sees it: the dimension d, the lane's
@@ -200,7 +182,7 @@ __device__ __forceinline__ void pair_row(PairLds<P>& sh, const PairEvent& e, int
   const float ex = exp2_fast(e.brow * e.z);
   const float R = ex * e.Rrow - (e.z == 0.f ? e.c : 0.f);
   const float S = ex * fmaf(e.z, e.Rrow, e.Srow);
-  const float lam = pair_group_sum<P>(e.arow * R) + e.mud;
+  const float lam = group_sum<P>(e.arow * R) + e.mud;
   const bool ok = e.ok != 0.f;
   llp += (ok && lane == 0) ? __builtin_amdgcn_logf(lam) : 0.f;
   if constexpr (GRAD) {

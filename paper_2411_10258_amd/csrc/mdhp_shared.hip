@@ -188,7 +188,7 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
         d_n = jr < len ? (int)dw[j0 + jr] : 0;
       }
       // Gap of the next event (the exclusive scan's input).
-      float prev = P <= 16 ? row_shr<1>(dt) : __shfl_up(dt, 1, P);
+      float prev = P <= 16 ? row_shr<1>(dt) : wave_shr1(dt);  // lane 0 of each group: below
       prev = lane == 0 ? 0.f : prev;
       const float tau = later + group_scan<P>(prev, lane);
       if (valid) {
