@@ -16,6 +16,7 @@ struct mdhp_plan {
   bool lane_major = false;  // events stored lane-major per window (M <= 16, one decay)
   int64_t slots = 0;        // length of dt / d
   float* dt = nullptr;
+  float* tau = nullptr;    // per event T - t (FP64 difference, stored FP32), same slots as dt
   uint8_t* d = nullptr;
   int64_t* begin = nullptr;
   int32_t* n = nullptr;
@@ -67,7 +68,9 @@ mdhp_status hip_fail(hipError_t e, const char* where) { return mdhp_hip_fail(e, 
 
 // Sec. IV-B "Stage 1" counterpart: per event, the gap to the previous event
 // of the same window in FP64 (stored FP32; a positive gap never rounds to 0),
-// the u8 dimension id, and validation of order and domain.  With slot_begin
+// the distance T - t to the window's end (FP64, stored FP32; the compensator
+// of windows with a slow decay is summed from it), the u8 dimension id, and
+// validation of order and domain.  With slot_begin
 // the window's events go lane-major: event k of a window of n events lands
 // in slot slot_begin[w] + L (k mod c) + k / c, with L = lane_team(n, big_min) chunks
 // and c = ceil(n / L), so that chunk l (events l c .. l c + c - 1) is read
@@ -76,7 +79,8 @@ __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double
                                const int32_t* __restrict__ dim, const double* __restrict__ T,
                                const int64_t* __restrict__ slot_begin, int64_t big_min,
                                int64_t W, int M,
-                               float* __restrict__ dt, uint8_t* __restrict__ d8,
+                               float* __restrict__ dt, float* __restrict__ tau,
+                               uint8_t* __restrict__ d8,
                                float* __restrict__ end_gap, double* __restrict__ Tc,
                                int32_t* __restrict__ counts, int* flags) {
   __shared__ int cnt[MDHP_MAX_M];
@@ -103,6 +107,7 @@ __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double
       const int64_t k = i - b;
       const int64_t dst = slot_begin ? slot_begin[w] + L * (k % c) + k / c : i;
       dt[dst] = g > 0.f ? g : 0.f;
+      tau[dst] = (float)fmax(Tw - ti, 0.0);
       d8[dst] = (uint8_t)(di < 0 ? 0 : (di >= M ? 0 : di));
       if (counts && di >= 0 && di < M) atomicAdd(&cnt[di], 1);
     }
@@ -171,7 +176,7 @@ hipError_t eval_plan(const mdhp_plan* p, const float* mu, const float* alpha, co
 
 Events events_of(const mdhp_plan* p) {
   return Events{p->W,     p->dt,      p->d,     p->begin,  p->n,
-                p->T,     p->end_gap, p->order, p->counts, p->n_big};
+                p->T,     p->end_gap, p->order, p->counts, p->n_big, p->tau};
 }
 
 template <class T>
@@ -184,6 +189,7 @@ hipError_t dev_alloc(T** ptr, size_t count) {
 void free_plan(mdhp_plan* p) {
   if (!p) return;
   (void)hipFree(p->dt);
+  (void)hipFree(p->tau);
   (void)hipFree(p->d);
   (void)hipFree(p->begin);
   (void)hipFree(p->n);
@@ -288,6 +294,7 @@ mdhp_status build_plan(const mdhp_batch* b, int32_t M, int32_t beta_mode, int64_
                          : p->lane_major             ? lpc_lbfgs_workspace(M, W, p->n_big)
                                                      : shared_lbfgs_workspace(M, W);
   if ((e = dev_alloc(&p->dt, p->slots)) != hipSuccess ||
+      (e = dev_alloc(&p->tau, p->slots)) != hipSuccess ||
       (e = dev_alloc(&p->d, p->slots)) != hipSuccess ||
       (e = dev_alloc(&p->begin, W)) != hipSuccess || (e = dev_alloc(&p->n, W)) != hipSuccess ||
       (e = dev_alloc(&p->T, W)) != hipSuccess || (e = dev_alloc(&p->end_gap, W)) != hipSuccess ||
@@ -311,6 +318,7 @@ mdhp_status build_plan(const mdhp_batch* b, int32_t M, int32_t beta_mode, int64_
   e = hipGetLastError();
   if (e == hipSuccess && p->lane_major && p->slots > 0) {  // padding slots: gap 0, no dimension
     e = hipMemsetAsync(p->dt, 0, p->slots * sizeof(float), s);
+    if (e == hipSuccess) e = hipMemsetAsync(p->tau, 0, p->slots * sizeof(float), s);
     if (e == hipSuccess) e = hipMemsetAsync(p->d, 0xFF, p->slots, s);
   }
   if (e == hipSuccess && W > 0) {
@@ -323,8 +331,8 @@ mdhp_status build_plan(const mdhp_batch* b, int32_t M, int32_t beta_mode, int64_
     if (e == hipSuccess) {
       const int grid = (int)std::min<int64_t>(W, 65536);
       hipLaunchKernelGGL(prepare_kernel, dim3(grid), dim3(256), 0, s, b->offsets, b->t, b->dim,
-                         b->T, p->lane_major ? p->begin : nullptr, p->big_min, W, M, p->dt, p->d,
-                         p->end_gap, p->T, p->counts, p->flags);
+                         b->T, p->lane_major ? p->begin : nullptr, p->big_min, W, M, p->dt,
+                         p->tau, p->d, p->end_gap, p->T, p->counts, p->flags);
       e = hipGetLastError();
     }
   }

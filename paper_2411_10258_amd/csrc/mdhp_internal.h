@@ -41,7 +41,60 @@ struct Events {
   const int32_t* order;  // [W] window ids, largest first
   const int32_t* counts; // [W][M] events per dimension
   int64_t n_big;         // lane-major plans: windows of >= kBigWindow events (a prefix of order)
+  const float* tau;      // T - t per event (same slots as dt), FP64-computed
 };
+
+// Windows whose decay is slow against their length (beta T below the
+// kernel's threshold) take the compensator sums from the events' distances
+// to T: sum_k -expm1(-beta tau_k) / beta and sum_k h(beta tau_k) / beta,
+// h(x) = x e^{-x} + expm1(-x), every term of one sign.  The end-state form
+// N - E subtracts two nearly equal numbers there.
+// beta T below which the lane-major kernels (M <= 16) take the event form.
+constexpr double kSlowDecayLane = 8.0;
+// beta T below which the lane-per-dimension kernels (16 < M <= 64) take it.
+constexpr double kSlowDecayDim = 2.0;
+// min over pairs of beta_mn T below which the per-pair kernels take it.
+constexpr double kSlowDecayPair = 4.0;
+// Both by their Taylor series below x = 0.5 (to x^12, relative error below
+// 1e-9 there), above it from one exponential (cancellation at most ~4x).
+__device__ __forceinline__ float comp_q(float x) {  // 1 - e^{-x}
+  if (x < 0.5f) {
+    // sum_{j >= 1} (-1)^{j+1} x^j / j!
+    float p = -1.f / 479001600.f;
+    p = fmaf(p, x, 1.f / 39916800.f);
+    p = fmaf(p, x, -1.f / 3628800.f);
+    p = fmaf(p, x, 1.f / 362880.f);
+    p = fmaf(p, x, -1.f / 40320.f);
+    p = fmaf(p, x, 1.f / 5040.f);
+    p = fmaf(p, x, -1.f / 720.f);
+    p = fmaf(p, x, 1.f / 120.f);
+    p = fmaf(p, x, -1.f / 24.f);
+    p = fmaf(p, x, 1.f / 6.f);
+    p = fmaf(p, x, -1.f / 2.f);
+    p = fmaf(p, x, 1.f);
+    return x * p;
+  }
+  return 1.f - __expf(-x);
+}
+__device__ __forceinline__ float comp_h(float x) {  // x e^{-x} - (1 - e^{-x})
+  if (x < 0.5f) {
+    // -sum_{j >= 2} (-1)^j (j - 1) x^j / j!
+    float p = 11.f / 479001600.f;
+    p = fmaf(p, x, -10.f / 39916800.f);
+    p = fmaf(p, x, 9.f / 3628800.f);
+    p = fmaf(p, x, -8.f / 362880.f);
+    p = fmaf(p, x, 7.f / 40320.f);
+    p = fmaf(p, x, -6.f / 5040.f);
+    p = fmaf(p, x, 5.f / 720.f);
+    p = fmaf(p, x, -4.f / 120.f);
+    p = fmaf(p, x, 3.f / 24.f);
+    p = fmaf(p, x, -2.f / 6.f);
+    p = fmaf(p, x, 1.f / 2.f);
+    return -(x * x) * p;
+  }
+  const float e = __expf(-x);
+  return fmaf(x, e, e - 1.f);
+}
 
 // Fit options as the kernels read them.
 struct FitParams {

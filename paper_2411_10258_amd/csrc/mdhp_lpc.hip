@@ -314,6 +314,53 @@ __device__ __forceinline__ void for_steps(const float* __restrict__ dtw,
   }
 }
 
+// Compensator sums of a slowly decaying window from its events (the lane's
+// chunk: c slots, T apart; padding slots have tau 0 and no dimension): lane
+// m < MP gets qs = sum over source-m events of -expm1(-beta tau) and hs = the
+// sum of h(beta tau).  Four components per sweep over the events, so that
+// the few registers it needs leave the fit kernels' allocation alone.
+template <int MP, int NW>
+__device__ __forceinline__ void slow_decay_sums(Team<MP, NW>& sh, const float* __restrict__ tw,
+                                                const uint8_t* __restrict__ dw, int c, float beta,
+                                                double& qs, double& hs) {
+  constexpr int T = Team<MP, NW>::T;
+  const int t = team_tid<NW>();
+  const int lane = t & 63, wv = t >> 6;
+#pragma unroll 1
+  for (int m0 = 0; m0 < MP; m0 += 4) {
+    float q[4] = {0.f, 0.f, 0.f, 0.f}, h[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int j = 0; j < c; ++j) {
+      const int d = dw[(int64_t)j * T] - m0;
+      const float xk = beta * tw[(int64_t)j * T];
+      const float qk = comp_q(xk), hk = comp_h(xk);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        q[i] += d == i ? qk : 0.f;
+        h[i] += d == i ? hk : 0.f;
+      }
+    }
+    // gpart is free here (its G_R partials were summed before the last sync).
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double qt = wave_sum((double)q[i]), ht = wave_sum((double)h[i]);
+      if (lane == 0) {
+        sh.gpart[wv][m0 + i] = qt;
+        sh.gpart[wv][MP + m0 + i] = ht;
+      }
+    }
+  }
+  team_sync<NW>();
+  qs = hs = 0.0;
+  if (t < MP) {
+#pragma unroll
+    for (int wk = 0; wk < NW; ++wk) {
+      qs += sh.gpart[wk][t];
+      hs += sh.gpart[wk][MP + t];
+    }
+  }
+}
+
 // Evaluates the team's window with the parameters in its LDS (alpha, mu,
 // colsum, beta; gmu cleared; counts = the window's N_m).  On return (all
 // lanes, after a team sync): scal[0] = ll; with GRAD also gR64 (G_R and, in
@@ -321,7 +368,8 @@ __device__ __forceinline__ void for_steps(const float* __restrict__ dtw,
 // spans of kSpan steps (MFMA) or over the lane's chunk, then FP64.
 template <int MP, int NW, bool GRAD>
 __device__ __forceinline__ void team_eval(Team<MP, NW>& sh, const float* __restrict__ dtg,
-                                          const uint8_t* __restrict__ dg, int64_t begin, int n,
+                                          const uint8_t* __restrict__ dg,
+                                          const float* __restrict__ taug, int64_t begin, int n,
                                           double Tw, float end_gap,
                                           const int32_t* __restrict__ counts, int M) {
   constexpr int Q = Team<MP, NW>::Q;
@@ -554,14 +602,19 @@ __device__ __forceinline__ void team_eval(Team<MP, NW>& sh, const float* __restr
     }
   }
   team_sync<NW>();
-  // Compensator: lane m < M finishes source dimension m.
+  // Compensator: lane m < M finishes source dimension m, from the end state
+  // (C = (N - E) / beta, F - C) or, for a slow decay, from the events.
   const double b = (double)beta;
+  const bool slow = b * Tw < kSlowDecayLane;  // uniform
+  double qs = 0.0, hs = 0.0;  // lane m: sum over source-m events of -expm1(-beta tau), h(beta tau)
+  if (slow) slow_decay_sums<MP, NW>(sh, taug + begin + t, dw, c, beta, qs, hs);
   double x = ll64, y = gb64;
   if (t < M) {
-    const double C = ((double)counts[t] - sh.En[t]) / b;
+    const double C = slow ? qs / b : ((double)counts[t] - sh.En[t]) / b;
+    const double FmC = slow ? hs / b : sh.Fn[t] - C;  // F_n - C_n
     const double cs = (double)sh.colsum[t];
     x -= Tw * (double)sh.mu[t] + cs * C;
-    y += cs * (sh.Fn[t] - C) / b;
+    y += cs * FmC / b;
     sh.Cn[t] = C;
   } else if (t < MP) {
     sh.Cn[t] = 0.0;
@@ -698,7 +751,7 @@ __device__ __forceinline__ void eval_one(Team<MP, NW>& sh, const Events& ev, int
   if constexpr (GRAD) team_zero(sh);
   team_load(sh, mu, alpha, beta, w, M);
   const double Tw = ev.T[w];
-  team_eval<MP, NW, GRAD>(sh, ev.dt, ev.d, ev.begin[w], ev.n[w], Tw, ev.end_gap[w],
+  team_eval<MP, NW, GRAD>(sh, ev.dt, ev.d, ev.tau, ev.begin[w], ev.n[w], Tw, ev.end_gap[w],
                           ev.counts + w * M, M);
   if (t == 0) ll[w] = sh.scal[0];
   if constexpr (GRAD) {
@@ -813,7 +866,7 @@ __device__ __forceinline__ void fit_one(Team<MP, NW>& sh, const Events& ev, int6
   int s = 0, st = MDHP_FIT_MAX_STEPS;
   for (s = 0;; ++s) {
     team_zero(sh);
-    team_eval<MP, NW, true>(sh, ev.dt, ev.d, ev.begin[w], n, Tw, ev.end_gap[w],
+    team_eval<MP, NW, true>(sh, ev.dt, ev.d, ev.tau, ev.begin[w], n, Tw, ev.end_gap[w],
                             ev.counts + w * M, M);
     const double l = uni(sh.scal[0]);
     double g[K];
@@ -941,7 +994,7 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
   // not finite.
   auto evaluate = [&]() -> bool {
     team_zero(sh);
-    team_eval<MP, NW, true>(sh, ev.dt, ev.d, ev.begin[w], n, Tw, ev.end_gap[w],
+    team_eval<MP, NW, true>(sh, ev.dt, ev.d, ev.tau, ev.begin[w], n, Tw, ev.end_gap[w],
                             ev.counts + w * M, M);
     bool bad = !isfinite(uni(sh.scal[0])) || !isfinite(uni(sh.scal[1]));
 #pragma unroll

@@ -193,6 +193,78 @@ __device__ __forceinline__ void pair_row(PairLds<P>& sh, const PairEvent& e, int
   }
 }
 
+// Whether some pair of the window decays slowly against its length (beta_mn
+// T below the threshold); uniform over the workgroup.  Uses sh.wsum.
+template <int P>
+__device__ __forceinline__ bool slow_decay_pair(PairLds<P>& sh, const PairOwn<P>& own, double T,
+                                                int M) {
+  using C = PairCfg<P>;
+  float bmin = 3.0e38f;
+#pragma unroll
+  for (int k = 0; k < C::OWN; ++k) {
+    const int e = threadIdx.x + k * C::THREADS;
+    if (e < P * P && e / P < M && e % P < M) bmin = fminf(bmin, own.beta[k]);
+  }
+  const double wmin = -wave_max(-(double)bmin);
+  __syncthreads();  // wsum: the previous window's readers are done
+  if ((threadIdx.x & 63) == 0) sh.wsum[threadIdx.x >> 6] = wmin;
+  __syncthreads();
+  double m = sh.wsum[0];
+  for (int v = 1; v < C::WAVES; ++v) m = fmin(m, sh.wsum[v]);
+  return m * T < kSlowDecayPair;
+}
+
+// Compensator sums of a slowly decaying window from its events.  Each chunk
+// adds, per event with source n = d and per target m (lane), -expm1(-x) and
+// h(x), x = beta_mn tau, into column n of its LDS state arrays (cleared
+// first, and by pass 1 after); the owner of pair (m, n) then sums the chunks
+// in FP64: C_mn = Q / beta_mn, F_mn = C_mn + H / beta_mn.
+template <int P>
+__device__ __noinline__ void slow_decay_sums_pair(PairLds<P>& sh, PairOwn<P>& own,
+                                                  const float* __restrict__ tw,
+                                                  const uint8_t* __restrict__ dw, int len,
+                                                  int nb, int lane, int grp, int M) {
+  using C = PairCfg<P>;
+  constexpr int Q = C::Q, B = C::B;
+  float* Qs = sh.Rs[grp];
+  float* Hs = sh.Ss[grp];
+  for (int e = lane; e < P * Q; e += P) {
+    Qs[e] = 0.f;
+    Hs[e] = 0.f;
+  }
+  for (int bb = 0; bb < nb; ++bb) {
+    const int jl = bb * B + (lane & (B - 1));
+    const float tau_l = jl < len ? tw[jl] : 0.f;  // null events: tau 0 adds nothing
+    const int d_l = jl < len ? (int)dw[jl] : 0;
+    static_for<B>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      const float tau = batch_bcast<P, j>(tau_l);
+      const int d = __builtin_bit_cast(int, batch_bcast<P, j>(__builtin_bit_cast(float, d_l)));
+      const float x = tau * (sh.nbeta[lane * Q + d] * (-1.f / kLog2e));
+      const int a = d * Q + lane;
+      Qs[a] += comp_q(x);
+      Hs[a] += comp_h(x);
+    });
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < C::OWN; ++k) {
+    const int e = threadIdx.x + k * C::THREADS;
+    if (e >= P * P) break;
+    const int m = e / P, n = e % P;
+    double q = 0.0, h = 0.0;
+    for (int g = 0; g < C::G; ++g) {
+      q += (double)sh.Rs[g][n * Q + m];
+      h += (double)sh.Ss[g][n * Q + m];
+    }
+    const bool in = m < M && n < M;
+    const double b = (double)own.beta[k];
+    own.C[k] = in ? q / b : 0.0;
+    own.F[k] = in ? q / b + h / b : 0.0;
+  }
+  __syncthreads();  // pass 1 clears the arrays next
+}
+
 // Evaluates one window with parameters in LDS (and the owned decays in
 // own.beta).  Results: sh.scal[0] = ll, own.C and own.F; if GRAD also sh.gR /
 // sh.gS (FP32 sums) and sh.gmu.
@@ -206,7 +278,8 @@ __device__ __forceinline__ void pair_row(PairLds<P>& sh, const PairEvent& e, int
 template <int P, bool GRAD>
 __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, PairOwn<P>& own,
                                                  const float* __restrict__ dtg,
-                                                 const uint8_t* __restrict__ dg, int64_t begin,
+                                                 const uint8_t* __restrict__ dg,
+                                                 const float* __restrict__ taug, int64_t begin,
                                                  int n, double T, float end_gap, int M) {
   using C = PairCfg<P>;
   constexpr int Q = C::Q, G = C::G, B = C::B;
@@ -226,6 +299,9 @@ __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, PairOwn<P>& own
     dt_l = jl < len ? dtw[j0 + jl] : 0.f;
     d_l = jl < len ? (int)dw[j0 + jl] : 0;
   };
+
+  const bool slow = slow_decay_pair<P>(sh, own, T, M);
+  if (slow) slow_decay_sums_pair<P>(sh, own, taug + begin + j0, dw + j0, len, nb, lane, grp, M);
 
   // Pass 1: zero-start state of this chunk, column updates only.
   for (int e = lane; e < P * Q; e += P) {
@@ -313,8 +389,10 @@ __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, PairOwn<P>& own
     const double E = ad * ((double)R + (double)Pc);
     const double F = ad * (double)S + gap * E;
     const bool in = m < M && nn < M;
-    own.C[k] = in ? ((double)Ntot - E) / bd : 0.0;
-    own.F[k] = in ? F : 0.0;
+    if (!slow) {
+      own.C[k] = in ? ((double)Ntot - E) / bd : 0.0;
+      own.F[k] = in ? F : 0.0;
+    }
   }
   __syncthreads();
   // Pass 2: from the exact chunk start, row reads (intensity, gradient
@@ -448,7 +526,7 @@ __global__ __launch_bounds__(PairCfg<P>::THREADS) void pair_eval_kernel(
     const int64_t w = ev.order[q];
     load_params_pair(sh, own, mu, alpha, beta, w, M);
     const double T = ev.T[w];
-    eval_window_pair<P, GRAD>(sh, own, ev.dt, ev.d, ev.begin[w], ev.n[w], T, ev.end_gap[w], M);
+    eval_window_pair<P, GRAD>(sh, own, ev.dt, ev.d, ev.tau, ev.begin[w], ev.n[w], T, ev.end_gap[w], M);
     if (tid == 0) ll[w] = sh.scal[0];
     if constexpr (GRAD) {
       if (tid < M) g_mu[w * M + tid] = (float)sh.gmu[tid];
@@ -496,7 +574,7 @@ __global__ __launch_bounds__(PairCfg<P>::THREADS) void pair_fit_kernel(
     double ll_prev = 0.0, b1t = 1.0, b2t = 1.0;
     int s = 0, st = MDHP_FIT_MAX_STEPS;
     for (s = 0;; ++s) {
-      eval_window_pair<P, true>(sh, own, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], M);
+      eval_window_pair<P, true>(sh, own, ev.dt, ev.d, ev.tau, ev.begin[w], n, T, ev.end_gap[w], M);
       const double l = sh.scal[0];
       // Gradient of the owned pairs (and reset of the FP32 sums).
       double ga[OWN], gb[OWN];

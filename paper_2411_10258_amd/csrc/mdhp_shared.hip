@@ -135,13 +135,79 @@ __device__ __forceinline__ float group_reduce_scatter(float (&v)[B]) {
   return z;
 }
 
+// Compensator sums of a slowly decaying window from its events: group g
+// takes chunk g of the window P events at a time, computing -expm1(-beta tau)
+// and h(beta tau) with a lane per event, then adding them event by event
+// with a lane per dimension.  On return lane n < P of the first group holds
+// the window's sums over source-n events in qs, hs.  Kept out of line (the
+// fit kernels' registers are full).
+template <int P>
+__device__ __noinline__ void slow_decay_sums(SharedLds<P>& sh, const float* __restrict__ tw,
+                                             const uint8_t* __restrict__ dw, int n, float beta,
+                                             double& qs, double& hs) {
+  constexpr int G = SharedLds<P>::G;
+  const int tid = threadIdx.x;
+  const int lane = tid & (P - 1);
+  const int grp = tid / P;
+  const int c = (n + G - 1) / G;
+  const int j0 = min(grp * c, n);
+  const int len = min(j0 + c, n) - j0;
+  const int nsub = (c + P - 1) / P;  // uniform
+  double q64 = 0.0, h64 = 0.0;
+  for (int sb = 0; sb < nsub; ++sb) {
+    const int j = sb * P + lane;
+    const bool ok = j < len;
+    const float x = ok ? beta * tw[j0 + j] : 0.f;
+    const float q = comp_q(x), h = comp_h(x);
+    const int d = ok ? (int)dw[j0 + j] : -1;
+    float qa = 0.f, ha = 0.f;
+    for (int k = 0; k < P; ++k) {
+      float qk, hk;
+      int dk;
+      if constexpr (P == 64) {
+        qk = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, q), k));
+        hk = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, h), k));
+        dk = __builtin_amdgcn_readlane(d, k);
+      } else if constexpr (P == 32) {  // two groups per wavefront
+        const bool hi = (tid & 32) != 0;
+        const int qi = __builtin_bit_cast(int, q), hi_ = __builtin_bit_cast(int, h);
+        qk = __builtin_bit_cast(float, hi ? __builtin_amdgcn_readlane(qi, 32 + k)
+                                          : __builtin_amdgcn_readlane(qi, k));
+        hk = __builtin_bit_cast(float, hi ? __builtin_amdgcn_readlane(hi_, 32 + k)
+                                          : __builtin_amdgcn_readlane(hi_, k));
+        dk = hi ? __builtin_amdgcn_readlane(d, 32 + k) : __builtin_amdgcn_readlane(d, k);
+      } else {
+        qk = __shfl(q, k, P);
+        hk = __shfl(h, k, P);
+        dk = __shfl(d, k, P);
+      }
+      qa += dk == lane ? qk : 0.f;
+      ha += dk == lane ? hk : 0.f;
+    }
+    q64 += (double)qa;
+    h64 += (double)ha;
+  }
+  sh.red[0][tid] = q64;
+  sh.red[1][tid] = h64;
+  __syncthreads();
+  qs = hs = 0.0;
+  if (tid < P) {
+    for (int g = 0; g < G; ++g) {
+      qs += sh.red[0][g * P + tid];
+      hs += sh.red[1][g * P + tid];
+    }
+  }
+  __syncthreads();  // red is reused by the caller
+}
+
 // Evaluates one window with the parameters already in LDS (alpha, mu,
 // colsum, beta).  Results: sh.scal[0] = ll, and if GRAD: gR64[k] holds
 // G_R[e] for e = tid + k * kBlock (FP64), sh.Cn, sh.Fn, sh.gmu (= d ll/d mu),
 // sh.scal[1] = d ll / d beta.  cnt_w: the window's events per dimension.
 template <int P, bool GRAD, int SB>
 __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __restrict__ dtg,
-                            const uint8_t* __restrict__ dg, int64_t begin, int n, double T,
+                            const uint8_t* __restrict__ dg, const float* __restrict__ taug,
+                            int64_t begin, int n, double T,
                             float end_gap, int M, const int32_t* __restrict__ cnt_w,
                             double (&gR64)[own_count(P)]) {
   constexpr int G = SharedLds<P>::G;
@@ -439,8 +505,12 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
   }
 
   // End of window: reduce the per-lane partials over groups (lane n of
-  // wave 0 takes component n), then the window sums over the wave.
+  // wave 0 takes component n), then the window sums over the wave.  A
+  // slowly decaying window takes its compensator sums from the events.
+  const bool slow = (double)beta * T < kSlowDecayDim;  // uniform
+  double qs = 0.0, hs = 0.0;
   __syncthreads();
+  if (slow) slow_decay_sums<P>(sh, taug + begin, dw, n, beta, qs, hs);
   sh.red[0][tid] = ll64;
   sh.red[1][tid] = gmu64;
   sh.red[2][tid] = gb64;
@@ -464,14 +534,15 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
       const double a = exp(-b * gap);
       const double E = a * ((double)sh.tR[tid] + (double)sh.tP[tid]);
       const double F = a * (double)sh.tS[tid] + gap * E;
-      const double C = (nn - E) / b;
+      const double C = slow ? qs / b : (nn - E) / b;
+      const double FmC = slow ? hs / b : F - C;  // F_n - C_n
       sh.Cn[tid] = in ? C : 0.0;
-      sh.Fn[tid] = in ? F : 0.0;
+      sh.Fn[tid] = in ? C + FmC : 0.0;
       sh.gmu[tid] = in ? gm - T : 0.0;
       p1 = l;                                                     // Part1
       smu = in ? (double)sh.mu[tid] : 0.0;                        // sum mu
       p3 = in ? (double)sh.colsum[tid] * C : 0.0;                 // Part3 (sign below)
-      gbeta = in ? gb + (double)sh.colsum[tid] * (F - C) / b : 0.0;  // -d ll / d beta
+      gbeta = in ? gb + (double)sh.colsum[tid] * FmC / b : 0.0;  // -d ll / d beta
     }
     p1 = wave_sum(p1);
     smu = wave_sum(smu);
@@ -541,7 +612,7 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_eva
     const int64_t w = ev.order[q];
     load_params(sh, mu, alpha, beta, w, M);
     const double T = ev.T[w];
-    eval_window<P, GRAD, SB>(sh, ev.dt, ev.d, ev.begin[w], ev.n[w], T, ev.end_gap[w], M, ev.counts + w * M, gR64);
+    eval_window<P, GRAD, SB>(sh, ev.dt, ev.d, ev.tau, ev.begin[w], ev.n[w], T, ev.end_gap[w], M, ev.counts + w * M, gR64);
     if (tid == 0) ll[w] = sh.scal[0];
     if constexpr (GRAD) {
       if (tid == 0) g_beta[w] = (float)sh.scal[1];
@@ -584,7 +655,7 @@ __global__ __launch_bounds__(kBlock, (P == 32 ? 2 : kMinBlocks)) void shared_fit
     double ll_prev = 0.0, b1t = 1.0, b2t = 1.0;
     int s = 0, st = MDHP_FIT_MAX_STEPS;
     for (s = 0;; ++s) {
-      eval_window<P, true, SB>(sh, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], M, ev.counts + w * M, gR64);
+      eval_window<P, true, SB>(sh, ev.dt, ev.d, ev.tau, ev.begin[w], n, T, ev.end_gap[w], M, ev.counts + w * M, gR64);
       const double l = sh.scal[0];
       // Finiteness of ll and of the whole gradient (one flag per block).
       if (tid == 0) sh.stop = isfinite(l) && isfinite(sh.scal[1]) ? 0 : 1;
@@ -780,7 +851,7 @@ __global__ __launch_bounds__(kBlock, (P == 32 ? 2 : kMinBlocks)) void shared_lbf
     };
     // Evaluates at the LDS parameters; true if ll and the gradient are finite.
     auto evaluate = [&]() -> bool {
-      eval_window<P, true, SB>(sh, ev.dt, ev.d, ev.begin[w], n, T, ev.end_gap[w], M, ev.counts + w * M, gR64);
+      eval_window<P, true, SB>(sh, ev.dt, ev.d, ev.tau, ev.begin[w], n, T, ev.end_gap[w], M, ev.counts + w * M, gR64);
       if (tid == 0) flag = isfinite(sh.scal[0]) && isfinite(sh.scal[1]) ? 0 : 1;
       __syncthreads();
       bool bad = false;
