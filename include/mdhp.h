@@ -215,7 +215,7 @@ typedef struct mdhp_tune_result {
   int32_t n;                    /* candidates timed */
   int32_t chosen;               /* index of the kept candidate */
   int32_t value[MDHP_TUNE_MAX]; /* candidate schedules */
-  float ms[MDHP_TUNE_MAX];      /* mean milliseconds per repetition */
+  float ms[MDHP_TUNE_MAX];      /* milliseconds of the fastest timed repetition */
 } mdhp_tune_result;
 
 /* Times every candidate schedule of the plan on its own windows from the

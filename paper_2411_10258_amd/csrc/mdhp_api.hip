@@ -618,7 +618,7 @@ mdhp_status mdhp_plan_autotune(mdhp_plan* p, const mdhp_batch* b, const mdhp_fit
     st = apply_schedule(p, b, v[i], s);
     if (st != MDHP_OK) break;
     st = mdhp_cold_start(p, mu0, al0, be0, s);
-    float total = 0.f;
+    float fastest = 0.f;
     for (int rep = 0; rep <= reps && st == MDHP_OK; ++rep) {  // rep 0 warms up
       if (o) {
         e = hipMemcpyAsync(mu, mu0, W * M * sizeof(float), hipMemcpyDeviceToDevice, s);
@@ -636,11 +636,11 @@ mdhp_status mdhp_plan_autotune(mdhp_plan* p, const mdhp_batch* b, const mdhp_fit
         break;
       float ms = 0.f;
       if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-      if (rep > 0) total += ms;
+      if (rep > 0) fastest = rep == 1 ? ms : std::min(fastest, ms);
     }
     if (e != hipSuccess && st == MDHP_OK) st = hip_fail(e, "autotune: timing");
     r->value[i] = v[i];
-    r->ms[i] = total / reps;
+    r->ms[i] = fastest;  // the least disturbed repetition
     r->n = i + 1;
     if (st == MDHP_OK && (best < 0 || r->ms[i] < r->ms[best])) best = i;
   }
