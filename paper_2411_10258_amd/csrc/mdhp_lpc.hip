@@ -317,7 +317,7 @@ __device__ __forceinline__ void for_steps(const float* __restrict__ dtw,
 // Compensator sums of a slowly decaying window from its events (the lane's
 // chunk: c slots, T apart; padding slots have tau 0 and no dimension): lane
 // m < MP gets qs = sum over source-m events of -expm1(-beta tau) and hs = the
-// sum of h(beta tau).  Four components per sweep over the events, so that
+// sum of h(beta tau).  One component per sweep over the events, so that
 // the few registers it needs leave the fit kernels' allocation alone.
 template <int MP, int NW>
 __device__ __forceinline__ void slow_decay_sums(Team<MP, NW>& sh, const float* __restrict__ tw,
@@ -327,27 +327,20 @@ __device__ __forceinline__ void slow_decay_sums(Team<MP, NW>& sh, const float* _
   const int t = team_tid<NW>();
   const int lane = t & 63, wv = t >> 6;
 #pragma unroll 1
-  for (int m0 = 0; m0 < MP; m0 += 4) {
-    float q[4] = {0.f, 0.f, 0.f, 0.f}, h[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < MP; ++m) {
+    float q = 0.f, h = 0.f;
 #pragma unroll 1
     for (int j = 0; j < c; ++j) {
-      const int d = dw[(int64_t)j * T] - m0;
+      if (dw[(int64_t)j * T] != m) continue;
       const float xk = beta * tw[(int64_t)j * T];
-      const float qk = comp_q(xk), hk = comp_h(xk);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        q[i] += d == i ? qk : 0.f;
-        h[i] += d == i ? hk : 0.f;
-      }
+      q += comp_q(xk);
+      h += comp_h(xk);
     }
     // gpart is free here (its G_R partials were summed before the last sync).
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const double qt = wave_sum((double)q[i]), ht = wave_sum((double)h[i]);
-      if (lane == 0) {
-        sh.gpart[wv][m0 + i] = qt;
-        sh.gpart[wv][MP + m0 + i] = ht;
-      }
+    const double qt = wave_sum((double)q), ht = wave_sum((double)h);
+    if (lane == 0) {
+      sh.gpart[wv][m] = qt;
+      sh.gpart[wv][MP + m] = ht;
     }
   }
   team_sync<NW>();
@@ -607,7 +600,7 @@ __device__ __forceinline__ void team_eval(Team<MP, NW>& sh, const float* __restr
   const double b = (double)beta;
   const bool slow = b * Tw < kSlowDecayLane;  // uniform
   double qs = 0.0, hs = 0.0;  // lane m: sum over source-m events of -expm1(-beta tau), h(beta tau)
-  if (slow) slow_decay_sums<MP, NW>(sh, taug + begin + t, dw, c, beta, qs, hs);
+  if (__builtin_expect(slow, 0)) slow_decay_sums<MP, NW>(sh, taug + begin + t, dw, c, beta, qs, hs);
   double x = ll64, y = gb64;
   if (t < M) {
     const double C = slow ? qs / b : ((double)counts[t] - sh.En[t]) / b;
