@@ -121,8 +121,9 @@ struct PairEvent {
 
 // Advances the lane's lazy clock to event J of the batch and issues every
 // LDS read the event needs.  Events past the chunk's end (J >= nv) are null:
-// no elapsed time, no count, no contribution.
-template <int P, int J>
+// no elapsed time, no count, no contribution.  FULL: the whole batch is
+// inside every chunk of the wavefront (no null events; the checks fold).
+template <int P, int J, bool FULL>
 __device__ __forceinline__ PairEvent pair_issue(PairLds<P>& sh, const float* Rs, const float* Ss,
                                                 int lane, float dt_l, int d_l, int nv, float& z,
                                                 float& cn) {
@@ -143,7 +144,7 @@ __device__ __forceinline__ PairEvent pair_issue(PairLds<P>& sh, const float* Rs,
   // The reads above stay ahead of the previous event's remaining work.
   __builtin_amdgcn_sched_barrier(0);
   const float dt = batch_bcast<P, J>(dt_l);
-  const bool ok = J < nv;
+  const bool ok = FULL || J < nv;
   z += dt;
   const float zd = group_lane<P>(z, d);
   e.z = z;
@@ -316,27 +317,34 @@ __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, PairOwn<P>& own
     for (int bb = 0; bb < nb; ++bb) {
       if (bb + 1 < nb) load(bb + 1, dt_n, d_n);
       const int nv = len - bb * B;
-      static_for<B>([&](auto J) {
-        constexpr int j = decltype(J)::value;
-        const int d = __builtin_bit_cast(int, batch_bcast<P, j>(__builtin_bit_cast(float, d_l)));
-        const int a = d * Q + lane;
-        const float Rt = Rs[a], St = Ss[a], bc = sh.nbeta[lane * Q + d];
-        __builtin_amdgcn_sched_barrier(0);  // reads first, the clock work under their latency
-        const float dt = batch_bcast<P, j>(dt_l);
-        const bool ok = j < nv;
-        z += dt;
-        delta += dt;
-        const float zd0 = group_lane<P>(z, d);
-        const float zd = ok ? zd0 : 0.f;
-        const float own = (ok && lane == d) ? 1.f : 0.f;
-        count += own;
-        const float ncn = zd > 0.f ? 1.f : cn + 1.f;
-        cn = fmaf(own, ncn - cn, cn);
-        z = fmaf(-own, z, z);
-        const float ec = exp2_fast(bc * zd);
-        Rs[a] = fmaf(ec, Rt, ok ? 1.f : 0.f);
-        Ss[a] = ec * fmaf(zd, Rt, St);
-      });
+      auto batch = [&](auto F) {
+        constexpr bool FULL = decltype(F)::value;
+        static_for<B>([&](auto J) {
+          constexpr int j = decltype(J)::value;
+          const int d = __builtin_bit_cast(int, batch_bcast<P, j>(__builtin_bit_cast(float, d_l)));
+          const int a = d * Q + lane;
+          const float Rt = Rs[a], St = Ss[a], bc = sh.nbeta[lane * Q + d];
+          __builtin_amdgcn_sched_barrier(0);  // reads first, the clock work under their latency
+          const float dt = batch_bcast<P, j>(dt_l);
+          const bool ok = FULL || j < nv;
+          z += dt;
+          delta += dt;
+          const float zd0 = group_lane<P>(z, d);
+          const float zd = ok ? zd0 : 0.f;
+          const float own = (ok && lane == d) ? 1.f : 0.f;
+          count += own;
+          const float ncn = zd > 0.f ? 1.f : cn + 1.f;
+          cn = fmaf(own, ncn - cn, cn);
+          z = fmaf(-own, z, z);
+          const float ec = exp2_fast(bc * zd);
+          Rs[a] = fmaf(ec, Rt, ok ? 1.f : 0.f);
+          Ss[a] = ec * fmaf(zd, Rt, St);
+        });
+      };
+      if (__ballot(nv < B) == 0)  // uniform over the wavefront
+        batch(std::true_type{});
+      else
+        batch(std::false_type{});
       dt_l = dt_n;
       d_l = d_n;
     }
@@ -409,18 +417,26 @@ __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, PairOwn<P>& own
     for (int bb = 0; bb < nb; ++bb) {
       if (bb + 1 < nb) load(bb + 1, dt_n, d_n);
       const int nv = len - bb * B;
-      PairEvent cur = pair_issue<P, 0>(sh, Rs, Ss, lane, dt_l, d_l, nv, z, cn);
-      static_for<B>([&](auto J) {
-        constexpr int j = decltype(J)::value;
-        pair_column(Rs, Ss, cur);
-        if constexpr (j + 1 < B) {
-          const PairEvent nxt = pair_issue<P, j + 1>(sh, Rs, Ss, lane, dt_l, d_l, nv, z, cn);
-          pair_row<P, GRAD>(sh, cur, lane, grp, llp, gmup);
-          cur = nxt;
-        } else {
-          pair_row<P, GRAD>(sh, cur, lane, grp, llp, gmup);
-        }
-      });
+      auto batch = [&](auto F) {
+        constexpr bool FULL = decltype(F)::value;
+        PairEvent cur = pair_issue<P, 0, FULL>(sh, Rs, Ss, lane, dt_l, d_l, nv, z, cn);
+        static_for<B>([&](auto J) {
+          constexpr int j = decltype(J)::value;
+          pair_column(Rs, Ss, cur);
+          if constexpr (j + 1 < B) {
+            const PairEvent nxt =
+                pair_issue<P, j + 1, FULL>(sh, Rs, Ss, lane, dt_l, d_l, nv, z, cn);
+            pair_row<P, GRAD>(sh, cur, lane, grp, llp, gmup);
+            cur = nxt;
+          } else {
+            pair_row<P, GRAD>(sh, cur, lane, grp, llp, gmup);
+          }
+        });
+      };
+      if (__ballot(nv < B) == 0)  // uniform over the wavefront
+        batch(std::true_type{});
+      else
+        batch(std::false_type{});
       dt_l = dt_n;
       d_l = d_n;
     }
