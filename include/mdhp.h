@@ -139,8 +139,9 @@ typedef struct mdhp_plan mdhp_plan;
  * Initialization" is the paper's counterpart).  Synchronous: runs the
  * preparation kernel on `stream`, waits for it and returns
  * MDHP_E_UNSORTED / MDHP_E_DOMAIN for bad events.  On success *out owns a
- * compact copy of the events (FP32 gaps computed in FP64, u8 dims), the
- * window order (largest first) and the workspace.  M in [1, 64] with
+ * compact copy of the events (FP32 gaps and FP32 distances T - t to the
+ * window's end, both computed in FP64, u8 dims: 9 B per event), the window
+ * order (largest first) and the workspace.  M in [1, 64] with
  * MDHP_BETA_SHARED, [1, 32] with MDHP_BETA_PAIR. */
 mdhp_status mdhp_plan_create(const mdhp_batch* batch, int32_t M, int32_t beta_mode, void* stream,
                              mdhp_plan** out);
@@ -155,8 +156,10 @@ int32_t mdhp_plan_dims(const mdhp_plan* plan);
 
 /* Log-likelihood of Eq. (5) per window: ll[W] (device f64).  Part1 is
  * evaluated by a segmented scan of the exponential-kernel recursion, Part2
- * and Part3 in closed form from the scan's end state (Appendix B); per-window
- * sums are reduced in FP64. */
+ * and Part3 in closed form (Appendix B) from the scan's end state, or, for a
+ * decay that is slow against the window (small beta T), from the events'
+ * distances to T, where the end-state form would cancel; per-window sums are
+ * reduced in FP64. */
 mdhp_status mdhp_loglik(mdhp_plan* plan, const float* mu, const float* alpha, const float* beta,
                         double* ll, void* stream);
 
