@@ -67,6 +67,16 @@ class TargetStats:
     def normalize(self, y):
         return ((y - self.mean) / self.std).astype(np.float32)
 
+    def on(self, device):
+        """(mean, std) as device tensors, copied once per device (a pageable
+        host-to-device copy waits for the stream's queued work)."""
+        cache = self.__dict__.setdefault("_on_device", {})
+        key = str(torch.device(device))
+        if key not in cache:
+            cache[key] = (torch.from_numpy(self.mean).to(device),
+                          torch.from_numpy(self.std).to(device))
+        return cache[key]
+
 
 class Surrogate:
     """MLP in_dim -> hidden -> hidden -> out_dim (mdhp_surrogate_*)."""
@@ -187,8 +197,7 @@ def warm_start(plan: Plan, surrogate: Surrogate, x: torch.Tensor, stats: TargetS
     opts = opts or FitOptions()
     dev = plan.device
     pred = surrogate.forward(x)
-    mean = torch.from_numpy(stats.mean).to(dev)
-    std = torch.from_numpy(stats.std).to(dev)
+    mean, std = stats.on(dev)
     mu_c, al_c, be_c = plan._params(mu_cold, alpha_cold, beta_cold)
     mu = torch.empty_like(mu_c)
     alpha = torch.empty_like(al_c)
