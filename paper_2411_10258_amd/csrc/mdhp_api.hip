@@ -17,6 +17,8 @@ struct mdhp_plan {
   int64_t slots = 0;        // length of dt / d
   float* dt = nullptr;
   float* tau = nullptr;    // per event T - t (FP64 difference, stored FP32), same slots as dt
+  float* gsd = nullptr;    // per-pair plans: per event the gap to the previous event of its
+                           // dimension in the window (FP64 difference, FP32; +inf if none)
   uint8_t* d = nullptr;
   int64_t* begin = nullptr;
   int32_t* n = nullptr;
@@ -126,6 +128,30 @@ __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double
   }
 }
 
+// Per-pair plans: per event, the time since the previous event of the same
+// dimension in its window (FP64 difference stored FP32; +inf for the first
+// of its dimension).  The per-pair kernels take a column's elapsed time from
+// it.  One thread per window walks its events in order, the last time of
+// each dimension in LDS; out-of-range dimensions were flagged by
+// prepare_kernel and are skipped here.
+__global__ void same_dim_gap_kernel(const int64_t* __restrict__ offsets,
+                                    const double* __restrict__ t,
+                                    const int32_t* __restrict__ dim, int64_t W, int M,
+                                    float* __restrict__ gsd) {
+  __shared__ double last[64][33];  // [thread][dimension], M <= 32 for per-pair plans
+  const int64_t w = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (w >= W) return;
+  double* lw = last[threadIdx.x];
+  for (int m = 0; m < M && m < 33; ++m) lw[m] = -1.0;
+  for (int64_t i = offsets[w]; i < offsets[w + 1]; ++i) {
+    const int d = dim[i];
+    if (d < 0 || d >= M || d >= 33) continue;
+    const double ti = t[i];
+    gsd[i] = lw[d] >= 0.0 ? (float)(ti - lw[d]) : __builtin_inff();
+    lw[d] = ti;
+  }
+}
+
 // Cold start (see mdhp_cold_start): one thread per parameter entry.
 __global__ void cold_start_kernel(const int32_t* __restrict__ counts, const double* __restrict__ T,
                                   int64_t W, int M, int pair, float* mu, float* alpha,
@@ -176,7 +202,7 @@ hipError_t eval_plan(const mdhp_plan* p, const float* mu, const float* alpha, co
 
 Events events_of(const mdhp_plan* p) {
   return Events{p->W,     p->dt,      p->d,     p->begin,  p->n,
-                p->T,     p->end_gap, p->order, p->counts, p->n_big, p->tau};
+                p->T,     p->end_gap, p->order, p->counts, p->n_big, p->tau, p->gsd};
 }
 
 template <class T>
@@ -190,6 +216,7 @@ void free_plan(mdhp_plan* p) {
   if (!p) return;
   (void)hipFree(p->dt);
   (void)hipFree(p->tau);
+  (void)hipFree(p->gsd);
   (void)hipFree(p->d);
   (void)hipFree(p->begin);
   (void)hipFree(p->n);
@@ -295,6 +322,7 @@ mdhp_status build_plan(const mdhp_batch* b, int32_t M, int32_t beta_mode, int64_
                                                      : shared_lbfgs_workspace(M, W);
   if ((e = dev_alloc(&p->dt, p->slots)) != hipSuccess ||
       (e = dev_alloc(&p->tau, p->slots)) != hipSuccess ||
+      (beta_mode == MDHP_BETA_PAIR && (e = dev_alloc(&p->gsd, p->slots)) != hipSuccess) ||
       (e = dev_alloc(&p->d, p->slots)) != hipSuccess ||
       (e = dev_alloc(&p->begin, W)) != hipSuccess || (e = dev_alloc(&p->n, W)) != hipSuccess ||
       (e = dev_alloc(&p->T, W)) != hipSuccess || (e = dev_alloc(&p->end_gap, W)) != hipSuccess ||
@@ -334,6 +362,11 @@ mdhp_status build_plan(const mdhp_batch* b, int32_t M, int32_t beta_mode, int64_
                          b->T, p->lane_major ? p->begin : nullptr, p->big_min, W, M, p->dt,
                          p->tau, p->d, p->end_gap, p->T, p->counts, p->flags);
       e = hipGetLastError();
+      if (e == hipSuccess && p->gsd) {
+        hipLaunchKernelGGL(same_dim_gap_kernel, dim3((unsigned)((W + 63) / 64)), dim3(64), 0, s,
+                           b->offsets, b->t, b->dim, W, M, p->gsd);
+        e = hipGetLastError();
+      }
     }
   }
   int flags = 0;

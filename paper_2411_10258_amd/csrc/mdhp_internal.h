@@ -42,6 +42,7 @@ struct Events {
   const int32_t* counts; // [W][M] events per dimension
   int64_t n_big;         // lane-major plans: windows of >= kBigWindow events (a prefix of order)
   const float* tau;      // T - t per event (same slots as dt), FP64-computed
+  const float* gsd;      // per-pair plans: gap to the previous event of the same dimension
 };
 
 // Windows whose decay is slow against their length (beta T below the

@@ -125,8 +125,8 @@ struct PairEvent {
 // inside every chunk of the wavefront (no null events; the checks fold).
 template <int P, int J, bool FULL>
 __device__ __forceinline__ PairEvent pair_issue(PairLds<P>& sh, const float* Rs, const float* Ss,
-                                                int lane, float dt_l, int d_l, int nv, float& z,
-                                                float& cn) {
+                                                int lane, float dt_l, int d_l, float g_l, int nv,
+                                                float& z, float& cn, float& dl) {
   constexpr int Q = PairCfg<P>::Q;
   PairEvent e;
   const int d = __builtin_bit_cast(int, batch_bcast<P, J>(__builtin_bit_cast(float, d_l)));
@@ -146,7 +146,10 @@ __device__ __forceinline__ PairEvent pair_issue(PairLds<P>& sh, const float* Rs,
   const float dt = batch_bcast<P, J>(dt_l);
   const bool ok = FULL || J < nv;
   z += dt;
-  const float zd = group_lane<P>(z, d);
+  dl += dt;
+  // Column d's elapsed time: since the previous source-d event, or since the
+  // chunk's start if that event lies before it.
+  const float zd = fminf(batch_bcast<P, J>(g_l), dl);
   e.z = z;
   e.c = cn;
   e.zd = ok ? zd : 0.f;
@@ -280,7 +283,8 @@ template <int P, bool GRAD>
 __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, PairOwn<P>& own,
                                                  const float* __restrict__ dtg,
                                                  const uint8_t* __restrict__ dg,
-                                                 const float* __restrict__ taug, int64_t begin,
+                                                 const float* __restrict__ taug,
+                                                 const float* __restrict__ gsdg, int64_t begin,
                                                  int n, double T, float end_gap, int M) {
   using C = PairCfg<P>;
   constexpr int Q = C::Q, G = C::G, B = C::B;
@@ -289,16 +293,18 @@ __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, PairOwn<P>& own
   const int grp = tid / P;
   const float* __restrict__ dtw = dtg + begin;
   const uint8_t* __restrict__ dw = dg + begin;
+  const float* __restrict__ gw = gsdg + begin;
   float* Rs = sh.Rs[grp];
   float* Ss = sh.Ss[grp];
   const int c = (n + G - 1) / G;
   const int j0 = min(grp * c, n);
   const int len = min(j0 + c, n) - j0;
   const int nb = (c + B - 1) / B;  // uniform over the workgroup; short chunks run null events
-  auto load = [&](int bb, float& dt_l, int& d_l) {
+  auto load = [&](int bb, float& dt_l, int& d_l, float& g_l) {
     const int jl = bb * B + (lane & (B - 1));
     dt_l = jl < len ? dtw[j0 + jl] : 0.f;
     d_l = jl < len ? (int)dw[j0 + jl] : 0;
+    g_l = jl < len ? gw[j0 + jl] : 0.f;
   };
 
   const bool slow = slow_decay_pair<P>(sh, own, T, M);
@@ -311,11 +317,11 @@ __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, PairOwn<P>& own
   }
   float z = 0.f, cn = 0.f, count = 0.f, delta = 0.f;
   {
-    float dt_l, dt_n = 0.f;
+    float dt_l, dt_n = 0.f, g_l, g_n = 0.f;
     int d_l, d_n = 0;
-    load(0, dt_l, d_l);
+    load(0, dt_l, d_l, g_l);
     for (int bb = 0; bb < nb; ++bb) {
-      if (bb + 1 < nb) load(bb + 1, dt_n, d_n);
+      if (bb + 1 < nb) load(bb + 1, dt_n, d_n, g_n);
       const int nv = len - bb * B;
       auto batch = [&](auto F) {
         constexpr bool FULL = decltype(F)::value;
@@ -329,7 +335,7 @@ __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, PairOwn<P>& own
           const bool ok = FULL || j < nv;
           z += dt;
           delta += dt;
-          const float zd0 = group_lane<P>(z, d);
+          const float zd0 = fminf(batch_bcast<P, j>(g_l), delta);  // column d's elapsed time
           const float zd = ok ? zd0 : 0.f;
           const float own = (ok && lane == d) ? 1.f : 0.f;
           count += own;
@@ -347,6 +353,7 @@ __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, PairOwn<P>& own
         batch(std::false_type{});
       dt_l = dt_n;
       d_l = d_n;
+      g_l = g_n;
     }
   }
   // Lazy columns -> full state at the chunk's last event (lane = column n).
@@ -411,21 +418,21 @@ __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, PairOwn<P>& own
     z = 0.f;
     cn = pend;
     float llp = 0.f, gmup = 0.f;  // llp: sum of log2 lambda
-    float dt_l, dt_n = 0.f;
+    float dt_l, dt_n = 0.f, g_l, g_n = 0.f, dl = 0.f;  // dl: time since the chunk's start
     int d_l, d_n = 0;
-    load(0, dt_l, d_l);
+    load(0, dt_l, d_l, g_l);
     for (int bb = 0; bb < nb; ++bb) {
-      if (bb + 1 < nb) load(bb + 1, dt_n, d_n);
+      if (bb + 1 < nb) load(bb + 1, dt_n, d_n, g_n);
       const int nv = len - bb * B;
       auto batch = [&](auto F) {
         constexpr bool FULL = decltype(F)::value;
-        PairEvent cur = pair_issue<P, 0, FULL>(sh, Rs, Ss, lane, dt_l, d_l, nv, z, cn);
+        PairEvent cur = pair_issue<P, 0, FULL>(sh, Rs, Ss, lane, dt_l, d_l, g_l, nv, z, cn, dl);
         static_for<B>([&](auto J) {
           constexpr int j = decltype(J)::value;
           pair_column(Rs, Ss, cur);
           if constexpr (j + 1 < B) {
             const PairEvent nxt =
-                pair_issue<P, j + 1, FULL>(sh, Rs, Ss, lane, dt_l, d_l, nv, z, cn);
+                pair_issue<P, j + 1, FULL>(sh, Rs, Ss, lane, dt_l, d_l, g_l, nv, z, cn, dl);
             pair_row<P, GRAD>(sh, cur, lane, grp, llp, gmup);
             cur = nxt;
           } else {
@@ -439,6 +446,7 @@ __device__ __forceinline__ void eval_window_pair(PairLds<P>& sh, PairOwn<P>& own
         batch(std::false_type{});
       dt_l = dt_n;
       d_l = d_n;
+      g_l = g_n;
     }
     sh.red[0][tid] = llp;
     sh.red[1][tid] = gmup;
@@ -542,7 +550,7 @@ __global__ __launch_bounds__(PairCfg<P>::THREADS) void pair_eval_kernel(
     const int64_t w = ev.order[q];
     load_params_pair(sh, own, mu, alpha, beta, w, M);
     const double T = ev.T[w];
-    eval_window_pair<P, GRAD>(sh, own, ev.dt, ev.d, ev.tau, ev.begin[w], ev.n[w], T, ev.end_gap[w], M);
+    eval_window_pair<P, GRAD>(sh, own, ev.dt, ev.d, ev.tau, ev.gsd, ev.begin[w], ev.n[w], T, ev.end_gap[w], M);
     if (tid == 0) ll[w] = sh.scal[0];
     if constexpr (GRAD) {
       if (tid < M) g_mu[w * M + tid] = (float)sh.gmu[tid];
@@ -590,7 +598,7 @@ __global__ __launch_bounds__(PairCfg<P>::THREADS) void pair_fit_kernel(
     double ll_prev = 0.0, b1t = 1.0, b2t = 1.0;
     int s = 0, st = MDHP_FIT_MAX_STEPS;
     for (s = 0;; ++s) {
-      eval_window_pair<P, true>(sh, own, ev.dt, ev.d, ev.tau, ev.begin[w], n, T, ev.end_gap[w], M);
+      eval_window_pair<P, true>(sh, own, ev.dt, ev.d, ev.tau, ev.gsd, ev.begin[w], n, T, ev.end_gap[w], M);
       const double l = sh.scal[0];
       // Gradient of the owned pairs (and reset of the FP32 sums).
       double ga[OWN], gb[OWN];
