@@ -140,8 +140,9 @@ typedef struct mdhp_plan mdhp_plan;
  * preparation kernel on `stream`, waits for it and returns
  * MDHP_E_UNSORTED / MDHP_E_DOMAIN for bad events.  On success *out owns a
  * compact copy of the events (FP32 gaps and FP32 distances T - t to the
- * window's end, both computed in FP64, u8 dims: 9 B per event), the window
- * order (largest first) and the workspace.  M in [1, 64] with
+ * window's end, both computed in FP64, u8 dims: 9 B per event; per-pair
+ * plans add the FP32 gap to the previous event of the same dimension: 13 B),
+ * the window order (largest first) and the workspace.  M in [1, 64] with
  * MDHP_BETA_SHARED, [1, 32] with MDHP_BETA_PAIR. */
 mdhp_status mdhp_plan_create(const mdhp_batch* batch, int32_t M, int32_t beta_mode, void* stream,
                              mdhp_plan** out);

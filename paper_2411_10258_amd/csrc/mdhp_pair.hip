@@ -90,23 +90,6 @@ __device__ __forceinline__ float batch_bcast(float x) {
     return group_bcast<P, J>(x);
 }
 
-// v of lane src of the caller's group (src uniform within the group).  At
-// P = 32 (two groups per wavefront) by lane reads into scalars; narrower
-// groups by a permute.
-template <int P>
-__device__ __forceinline__ float group_lane(float v, int src) {
-  if constexpr (P == 32) {
-    const int vi = __builtin_bit_cast(int, v);
-    const int s0 = __builtin_amdgcn_readlane(src, 0);
-    const int s1 = __builtin_amdgcn_readlane(src, 32) + 32;
-    const int a = __builtin_amdgcn_readlane(vi, s0);
-    const int b = __builtin_amdgcn_readlane(vi, s1);
-    return __builtin_bit_cast(float, (threadIdx.x & 32) ? b : a);
-  } else {
-    return __shfl(v, src, P);
-  }
-}
-
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // One event of a chunk as a lane sees it: the dimension d, the lane's
