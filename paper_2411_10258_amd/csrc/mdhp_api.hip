@@ -71,8 +71,9 @@ mdhp_status hip_fail(hipError_t e, const char* where) { return mdhp_hip_fail(e, 
 // Sec. IV-B "Stage 1" counterpart: per event, the gap to the previous event
 // of the same window in FP64 (stored FP32; a positive gap never rounds to 0),
 // the distance T - t to the window's end (FP64, stored FP32; the compensator
-// of windows with a slow decay is summed from it), the u8 dimension id, and
-// validation of order and domain.  With slot_begin
+// of windows with a slow decay is summed from it), for per-pair plans (gsd)
+// the gap to the previous event of the same dimension, the u8 dimension id,
+// and validation of order and domain.  With slot_begin
 // the window's events go lane-major: event k of a window of n events lands
 // in slot slot_begin[w] + L (k mod c) + k / c, with L = lane_team(n, big_min) chunks
 // and c = ceil(n / L), so that chunk l (events l c .. l c + c - 1) is read
@@ -82,7 +83,7 @@ __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double
                                const int64_t* __restrict__ slot_begin, int64_t big_min,
                                int64_t W, int M,
                                float* __restrict__ dt, float* __restrict__ tau,
-                               uint8_t* __restrict__ d8,
+                               float* __restrict__ gsd, uint8_t* __restrict__ d8,
                                float* __restrict__ end_gap, double* __restrict__ Tc,
                                int32_t* __restrict__ counts, int* flags) {
   __shared__ int cnt[MDHP_MAX_M];
@@ -110,6 +111,13 @@ __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double
       const int64_t dst = slot_begin ? slot_begin[w] + L * (k % c) + k / c : i;
       dt[dst] = g > 0.f ? g : 0.f;
       tau[dst] = (float)fmax(Tw - ti, 0.0);
+      if (gsd && di >= 0 && di < M) {
+        // Time since the previous event of the same dimension (+inf if
+        // none): over a window the searches add up to at most M n steps.
+        int64_t j = i - 1;
+        while (j >= b && dim[j] != di) --j;
+        gsd[dst] = j >= b ? (float)(ti - t[j]) : __builtin_inff();
+      }
       d8[dst] = (uint8_t)(di < 0 ? 0 : (di >= M ? 0 : di));
       if (counts && di >= 0 && di < M) atomicAdd(&cnt[di], 1);
     }
@@ -125,30 +133,6 @@ __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double
       Tc[w] = Tw;
     }
     if (err) atomicOr(flags, err);
-  }
-}
-
-// Per-pair plans: per event, the time since the previous event of the same
-// dimension in its window (FP64 difference stored FP32; +inf for the first
-// of its dimension).  The per-pair kernels take a column's elapsed time from
-// it.  One thread per window walks its events in order, the last time of
-// each dimension in LDS; out-of-range dimensions were flagged by
-// prepare_kernel and are skipped here.
-__global__ void same_dim_gap_kernel(const int64_t* __restrict__ offsets,
-                                    const double* __restrict__ t,
-                                    const int32_t* __restrict__ dim, int64_t W, int M,
-                                    float* __restrict__ gsd) {
-  __shared__ double last[64][33];  // [thread][dimension], M <= 32 for per-pair plans
-  const int64_t w = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (w >= W) return;
-  double* lw = last[threadIdx.x];
-  for (int m = 0; m < M && m < 33; ++m) lw[m] = -1.0;
-  for (int64_t i = offsets[w]; i < offsets[w + 1]; ++i) {
-    const int d = dim[i];
-    if (d < 0 || d >= M || d >= 33) continue;
-    const double ti = t[i];
-    gsd[i] = lw[d] >= 0.0 ? (float)(ti - lw[d]) : __builtin_inff();
-    lw[d] = ti;
   }
 }
 
@@ -360,13 +344,8 @@ mdhp_status build_plan(const mdhp_batch* b, int32_t M, int32_t beta_mode, int64_
       const int grid = (int)std::min<int64_t>(W, 65536);
       hipLaunchKernelGGL(prepare_kernel, dim3(grid), dim3(256), 0, s, b->offsets, b->t, b->dim,
                          b->T, p->lane_major ? p->begin : nullptr, p->big_min, W, M, p->dt,
-                         p->tau, p->d, p->end_gap, p->T, p->counts, p->flags);
+                         p->tau, p->gsd, p->d, p->end_gap, p->T, p->counts, p->flags);
       e = hipGetLastError();
-      if (e == hipSuccess && p->gsd) {
-        hipLaunchKernelGGL(same_dim_gap_kernel, dim3((unsigned)((W + 63) / 64)), dim3(64), 0, s,
-                           b->offsets, b->t, b->dim, W, M, p->gsd);
-        e = hipGetLastError();
-      }
     }
   }
   int flags = 0;
