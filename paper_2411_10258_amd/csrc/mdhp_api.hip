@@ -113,10 +113,18 @@ __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double
       tau[dst] = (float)fmax(Tw - ti, 0.0);
       if (gsd && di >= 0 && di < M) {
         // Time since the previous event of the same dimension (+inf if
-        // none): over a window the searches add up to at most M n steps.
+        // none), FP64 difference stored FP32; a positive gap never rounds
+        // to 0 (0 means "same time", a tie).  Per dimension the searches
+        // telescope to at most n steps, plus at most n for its first
+        // event: about 2 M n steps per window, one thread per event.
         int64_t j = i - 1;
         while (j >= b && dim[j] != di) --j;
-        gsd[dst] = j >= b ? (float)(ti - t[j]) : __builtin_inff();
+        float gs = __builtin_inff();
+        if (j >= b) {
+          gs = (float)(ti - t[j]);
+          if (ti > t[j] && !(gs > 0.f)) gs = 1.17549435e-38f;
+        }
+        gsd[dst] = gs;
       }
       d8[dst] = (uint8_t)(di < 0 ? 0 : (di >= M ? 0 : di));
       if (counts && di >= 0 && di < M) atomicAdd(&cnt[di], 1);

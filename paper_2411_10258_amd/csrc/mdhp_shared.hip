@@ -30,7 +30,10 @@
 // event; the reciprocals return through LDS and G_R[d_i][n] += R_n(i) /
 // lambda_i is one LDS add per event and lane (lane n owns column n, so the
 // adds of one event never collide).  The pending one-hot row [d_i = n] is
-// read from LDS next to alpha_{d_i n}.
+// read from LDS next to alpha_{d_i n}.  LDS sums that several lanes add to
+// (chunk carries, G_R at P = 32, Gmu) have one copy per group or wavefront:
+// adds from different wavefronts never meet, and the copies are summed in a
+// fixed order, so that a window's results do not depend on timing.
 // The compensator (Part2 + Part3, Appendix B) needs
 //   E_n = sum_{k: d_k = n} e^{-beta (T - t_k)},  F_n = sum (T - t_k) e^{-beta (T - t_k)},
 // which are the scan state advanced from the last event to T.
@@ -57,7 +60,11 @@ template <int P>
 struct SharedLds {
   static constexpr bool kLaneDim = P >= 32;            // pass 2 by reduce-scatter
   static constexpr int G = kBlock / P;                 // groups (chunks) per tile
-  static constexpr int NCOPY = kLaneDim ? 1 : kBlock / 64;  // G_R copies (one per wave if small)
+  // G_R copies: one per wavefront wherever its lanes add into LDS (only the
+  // register form at P = 64 needs a single transfer buffer), so that adds
+  // from different wavefronts never meet and the sums do not depend on
+  // timing.
+  static constexpr int NCOPY = P == 64 ? 1 : kBlock / 64;
   static constexpr int AR = kLaneDim ? P + 1 : P;      // rows of ao and gR (row P: padding events)
   static constexpr int NG = kLaneDim ? G : 1;
   // .x: alpha[m * P + n], zero outside M x M and in row P; .y: [m == n].
@@ -71,7 +78,7 @@ struct SharedLds {
   float gR[NCOPY][AR * P];    // FP32 tile partials of G_R
   float4 meta[NG][P];         // per group: a, dt, d (bits), mu_d (-1: padding) of a block
   float wb[NG][16];           // per group: 1 / lambda of a reduce-scatter's events
-  float gmuL[P + 1];          // FP32 Gmu partials (row P: padding)
+  float gmuL[NG][P + 1];      // per group: FP32 Gmu partials (entry P: padding)
   double red[4][kBlock];      // end-of-window reductions
   double Cn[P];               // (N_n - E_n) / beta
   double Fn[P];               // F_n
@@ -223,7 +230,8 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
 
   double ll64 = 0.0, gmu64 = 0.0, gb64 = 0.0;
   if constexpr (SharedLds<P>::kLaneDim) {
-    if (tid <= P) sh.gmuL[tid] = 0.f;  // ordered before pass 2 by the barriers below
+    // Ordered before pass 2 by the barriers below.
+    for (int e = tid; e < SharedLds<P>::NG * (P + 1); e += kBlock) (&sh.gmuL[0][0])[e] = 0.f;
   }
   // Group g owns the contiguous chunk [j0, j1) of the window.
   const int c = (n + G - 1) / G;
@@ -241,9 +249,12 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
     sh.cP[grp][lane] = 0.f;
     float later = 0.f;
     const int nsub = (c + P - 1) / P;
-    int jr = (nsub - 1) * P + (P - 1 - lane);  // lanes run backwards through a sub-batch
-    float dt_n = jr < len ? dtw[j0 + jr] : 0.f;
-    int d_n = jr < len ? (int)dw[j0 + jr] : 0;
+    // Lanes run backwards through a sub-batch.  An empty window has no
+    // sub-batch (nsub = 0) and jr < 0: nothing may be read there, the window
+    // may start at the first event of the plan's arrays.
+    int jr = (nsub - 1) * P + (P - 1 - lane);
+    float dt_n = (jr >= 0 && jr < len) ? dtw[j0 + jr] : 0.f;
+    int d_n = (jr >= 0 && jr < len) ? (int)dw[j0 + jr] : 0;
     for (int bb = nsub - 1; bb >= 0; --bb) {
       const bool valid = jr < len;
       const float dt = dt_n;
@@ -318,6 +329,7 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
     const bool lead = (lane & ((1 << SH) - 1)) == 0;
     float4* meta = sh.meta[SharedLds<P>::NG > 1 ? grp : 0];
     float* wb = sh.wb[SharedLds<P>::NG > 1 ? grp : 0];
+    float* gmuL = sh.gmuL[SharedLds<P>::NG > 1 ? grp : 0];
     float R = sh.cR[grp][lane], S = sh.cS[grp][lane];
     float Rin = R + sh.cP[grp][lane];  // R plus the events pending at the current time
     float llp = 0.f, gbp = 0.f;
@@ -366,7 +378,7 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
           const float w = valid ? __builtin_amdgcn_rcpf(lam) : 0.f;
           if (lead) {
             wb[ev_l] = w;
-            if (valid) atomicAdd(&sh.gmuL[__builtin_bit_cast(int, me.z)], w);
+            if (valid) atomicAdd(&gmuL[__builtin_bit_cast(int, me.z)], w);
           }
           wave_sync();
           float wv[B];
@@ -389,7 +401,7 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
               gacc0[dl] += hi ? 0.f : x;
               gacc1[dl] += hi ? x : 0.f;
             } else {
-              atomicAdd(&sh.gR[0][Dj[j] * P + lane], x);
+              atomicAdd(&gRc[Dj[j] * P + lane], x);
             }
             gbp = fmaf(wv[j], AS[j], gbp);
           }
@@ -525,7 +537,11 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
         gm += sh.red[1][g * P + tid];
         gb += sh.red[2][g * P + tid];
       }
-      if constexpr (SharedLds<P>::kLaneDim) gm = (double)sh.gmuL[tid];
+      if constexpr (SharedLds<P>::kLaneDim) {
+        gm = 0.0;
+#pragma unroll 1
+        for (int g = 0; g < SharedLds<P>::NG; ++g) gm += (double)sh.gmuL[g][tid];
+      }
       const bool in = tid < M;
       const double nn = in ? (double)cnt_w[tid] : 0.0;
       // Advance the end state to T: E_n and F_n of the compensator.
