@@ -38,8 +38,10 @@
  *   read parameter values on the host, so invalid parameter values (mu <= 0,
  *   alpha < 0, beta <= 0, non-finite) give non-finite results for the
  *   affected windows instead of an error code; mdhp_fit_batch reports them
- *   per window as MDHP_FIT_NONFINITE.  mdhp_last_error() returns a message
- *   for the last failing call on the calling thread.
+ *   per window as MDHP_FIT_NONFINITE, or, asked to check its initial values
+ *   (mdhp_fit_opts.check_params), returns MDHP_E_PARAM; mdhp_check_params
+ *   checks any parameter set.  mdhp_last_error() returns a message for the
+ *   last failing call on the calling thread.
  */
 #ifndef MDHP_H_
 #define MDHP_H_
@@ -59,7 +61,8 @@ enum {
   MDHP_E_DOMAIN = -3,   /* t < 0, t > T, dim outside [0, M), T <= 0 or not finite */
   MDHP_E_PARAM = -4,    /* invalid parameter value (checked by the helpers below) */
   MDHP_E_NOMEM = -5,    /* device allocation failed */
-  MDHP_E_HIP = -6       /* a HIP runtime call failed */
+  MDHP_E_HIP = -6,      /* a HIP runtime call failed */
+  MDHP_E_IO = -7        /* a checkpoint file could not be written or read, or is not one */
 };
 
 enum { MDHP_BETA_SHARED = 0, MDHP_BETA_PAIR = 1 };
@@ -120,7 +123,16 @@ typedef struct mdhp_batch {
  * s.y > 1e-10 |s| |y|.  The window stops as converged when an accepted step
  * changes ll by at most ll_tol * max(|ll|, N_w, 1) or the free gradient is zero,
  * as MAX_STEPS after max_steps accepted steps, and as STALLED when no trial
- * is accepted.  lr, adam_* are not used. */
+ * is accepted.  lr, adam_* are not used.
+ *
+ * check_params: non-zero makes mdhp_fit_batch validate the initial values
+ * first (mu > 0, alpha >= 0, beta > 0, all finite: the domain of Eq. (2)
+ * and Eq. (5)) and return MDHP_E_PARAM without fitting if any window
+ * violates them; the call then waits for the check on `stream` (so it must
+ * not be captured into a graph).  Zero (the default) keeps the call
+ * asynchronous: initial values are not read on the host, the first update
+ * projects them onto the feasible set, and a window whose evaluation is not
+ * finite ends as MDHP_FIT_NONFINITE. */
 typedef struct mdhp_fit_opts {
   int32_t max_steps; /* >= 0 */
   int32_t optimizer; /* MDHP_OPT_PGD, MDHP_OPT_PADAM or MDHP_OPT_LBFGS */
@@ -131,6 +143,8 @@ typedef struct mdhp_fit_opts {
   double mu_floor_rel;
   double beta_floor_rel;
   double adam_b1, adam_b2, adam_eps;
+  int32_t check_params; /* non-zero: validate the initial values (synchronous) */
+  int32_t reserved;     /* 0 */
 } mdhp_fit_opts;
 
 typedef struct mdhp_plan mdhp_plan;
@@ -309,6 +323,28 @@ mdhp_status mdhp_surrogate_adam(mdhp_surrogate* s, float lr, float b1, float b2,
 mdhp_status mdhp_surrogate_train_step(mdhp_surrogate* s, const uint16_t* x, int32_t B,
                                       const float* target, float lr, double* loss,
                                       void* stream);
+
+/* Checkpoint of a surrogate, for resuming training or serving a trained
+ * network (the library's addition; the paper has no learned warm start).
+ * File layout (host byte order, little-endian on every supported host):
+ *   char magic[8] = "MDHPSUR1"; int32 version = 1; int32 in_dim, hidden,
+ *   out_dim; int64 n_params; int64 adam_step; int64 n_extra;
+ *   float32 weights[n_params]; float32 adam_m1[n_params];
+ *   float32 adam_m2[n_params]; float32 extra[n_extra].
+ * `extra` (host memory, may be NULL when n_extra is 0) is caller data kept
+ * with the network, e.g. the normalisation of its targets.
+ * save: waits for `stream`, copies the FP32 master weights and both Adam
+ * moments to the host and writes them with the step count; MDHP_E_IO if the
+ * file cannot be written.
+ * load: reads such a file into a surrogate of the same in_dim, hidden and
+ * out_dim (else MDHP_E_INVAL), restores weights, moments and step, refreshes
+ * the BF16 copy and waits for `stream`; MDHP_E_IO for a missing, truncated
+ * or foreign file.  *n_extra receives the stored extra count; at most
+ * extra_cap values are copied to extra (NULL: none). */
+mdhp_status mdhp_surrogate_save(mdhp_surrogate* s, const char* path, const float* extra,
+                                int64_t n_extra, void* stream);
+mdhp_status mdhp_surrogate_load(mdhp_surrogate* s, const char* path, float* extra,
+                                int64_t extra_cap, int64_t* n_extra, void* stream);
 
 /* Warm start for a plan with one decay per window.  pred[W][M + M*M + 1]
  * (device f32) is the network output for the plan's windows, in z-scored

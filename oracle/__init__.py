@@ -9,8 +9,9 @@ Three parts, each written from the paper ("MDHP-Net", Sec. II-B, Sec. IV-B,
 Appendices A and B):
 
 * ``liboracle.so`` (``mdhp_oracle.cpp``): Eq. (5) by brute force and by the
-  exponential-kernel recursion, the term-by-term gradient, and the projected
-  gradient fit, all in FP64 on host threads.
+  exponential-kernel recursion (per pair, and with one decay shared by every
+  pair), the term-by-term gradient, the tolerance scales, and the projected
+  gradient fits, all in FP64 on host threads.
 * ``brute.py``: a second, pure-Python brute force of Eq. (5) for tiny inputs.
 * ``quadrature.py``: the integral Gamma of Eq. (4) by numerical quadrature,
   which checks the closed form of Appendix B independently.
@@ -56,6 +57,8 @@ def _load():
         lib.mdhp_oracle_grad_brute.argtypes = eval_args + [P, P, P, I32]
         lib.mdhp_oracle_fit.argtypes = [P, P, P, P, I64, I32, I32, P, P, P, P, P, P, P, P, I32]
         lib.mdhp_oracle_scales.argtypes = eval_args + [P, P, P, I32]
+        lib.mdhp_oracle_set_pairwise_shared.argtypes = [I32]
+        lib.mdhp_oracle_set_pairwise_shared.restype = None
         for f in (lib.mdhp_oracle_loglik, lib.mdhp_oracle_loglik_brute,
                   lib.mdhp_oracle_grad, lib.mdhp_oracle_grad_brute, lib.mdhp_oracle_fit,
                   lib.mdhp_oracle_scales,
@@ -89,6 +92,13 @@ def _params(W, M, mu, alpha, beta, beta_mode):
     beta = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, np.float64), bshape),
                                 dtype=np.float64)
     return mu, alpha, beta
+
+
+def set_pairwise_shared(on: bool) -> None:
+    """Shared-decay windows take the per-pair recursion (the decay copied
+    into every pair) instead of the O(N M) shared form: the cross-check of
+    the two forms."""
+    _load().mdhp_oracle_set_pairwise_shared(1 if on else 0)
 
 
 def default_threads() -> int:

@@ -21,6 +21,8 @@
 //   * recursion: the same sums with Part1's inner double sum replaced by the
 //                standard exponential-kernel recursion (Ozaki, cited by the
 //                paper for Eq. (1)), O(N M^2) per window; exact up to rounding.
+//                With one decay for every pair the recursion depends on the
+//                source only: O(N M) per window (recursion_window_shared).
 //   * fit:       projected gradient ascent on ll / max(N, 1) (plain step or
 //                Adam step), projection mu >= mu_min, alpha >= 0,
 //                beta >= beta_min; the paper uses "a PyTorch optimizer" on
@@ -59,6 +61,7 @@ struct Window {
 struct Params {
   int M;
   std::vector<double> mu, alpha, beta;  // M, M*M, M*M
+  bool shared = false;                  // one decay for every pair (beta_mode 0)
 };
 
 Params load_params(int M, int beta_mode, const double* mu, const double* alpha,
@@ -70,6 +73,7 @@ Params load_params(int M, int beta_mode, const double* mu, const double* alpha,
   p.beta.resize((size_t)M * M);
   for (int i = 0; i < M * M; ++i)
     p.beta[i] = beta_mode == 0 ? beta[w] : beta[w * M * M + i];
+  p.shared = beta_mode == 0;
   return p;
 }
 
@@ -287,6 +291,94 @@ double recursion_window(const Window& win, const Params& p, Grad* g, Scale* sc =
   return part1 + part2 + part3;
 }
 
+// Recursion with one decay for every pair (beta_mn = beta, the shared mode):
+// R_mn(i) = R_n(i) and S_mn(i) = S_n(i) depend on the source only, and so
+// do the compensator's sums, so a time step costs one exponential and O(M)
+// work instead of M^2 exponentials.  Same sums, same outputs as
+// recursion_window (which the shared mode can be forced back to, for the
+// cross-check of the two).
+bool g_pairwise_shared = false;
+
+double recursion_window_shared(const Window& win, const Params& p, Grad* g, Scale* sc) {
+  const int M = p.M;
+  const int MM = M * M;
+  const double b = p.beta[0];
+  std::vector<double> R(M, 0.0), S(M, 0.0), pend(M, 0.0);
+  std::vector<double> gR(MM, 0.0), gS(MM, 0.0), gmu(M, 0.0);
+  double t_prev = 0.0;
+  double part1 = 0.0, abs1 = 0.0;
+  for (int64_t i = 0; i < win.n; ++i) {
+    const double dt = win.t[i] - t_prev;
+    if (dt > 0.0) {
+      const double a = std::exp(-b * dt);
+      for (int n = 0; n < M; ++n) {
+        const double r = a * (R[n] + pend[n]);
+        S[n] = a * S[n] + dt * r;
+        R[n] = r;
+      }
+      std::fill(pend.begin(), pend.end(), 0.0);
+      t_prev = win.t[i];
+    }
+    const int m = win.d[i];
+    double lam = p.mu[m];
+    for (int n = 0; n < M; ++n) lam += p.alpha[m * M + n] * R[n];
+    part1 += std::log(lam);
+    abs1 += std::fabs(std::log(lam));
+    if (g || sc) {
+      const double w = 1.0 / lam;
+      gmu[m] += w;
+      for (int n = 0; n < M; ++n) {
+        gR[m * M + n] += w * R[n];
+        gS[m * M + n] += w * S[n];
+      }
+    }
+    pend[m] += 1.0;
+  }
+  double sum_mu = 0.0;
+  for (int m = 0; m < M; ++m) sum_mu += p.mu[m];
+  const double part2 = -win.T * sum_mu;
+  // Part3: sums over the source-n events, the same for every target.
+  std::vector<double> s(M, 0.0), s_tau(M, 0.0);
+  for (int64_t k = 0; k < win.n; ++k) {
+    const int n = win.d[k];
+    const double tau = win.T - win.t[k];
+    s[n] += std::expm1(-b * tau);
+    s_tau[n] += tau * std::exp(-b * tau);
+  }
+  double part3 = 0.0;
+  for (int i = 0; i < MM; ++i) part3 += p.alpha[i] / b * s[i % M];
+  if (sc) {
+    sc->ll = abs1 + win.T * sum_mu - part3;
+    sc->mu.resize(M);
+    sc->alpha.resize(MM);
+    sc->beta.resize(MM);
+    for (int m = 0; m < M; ++m) sc->mu[m] = gmu[m] + win.T;
+    for (int i = 0; i < MM; ++i) {
+      const double a = p.alpha[i], sn = s[i % M];
+      sc->alpha[i] = gR[i] + std::fabs(sn) / b;
+      sc->beta[i] = a * gS[i] + a / (b * b) * std::fabs(sn) + a / b * s_tau[i % M];
+    }
+  }
+  if (g) {
+    g->mu.resize(M);
+    g->alpha.resize(MM);
+    g->beta.resize(MM);
+    for (int m = 0; m < M; ++m) g->mu[m] = gmu[m] - win.T;
+    for (int i = 0; i < MM; ++i) {
+      const double a = p.alpha[i], sn = s[i % M];
+      g->alpha[i] = gR[i] + sn / b;
+      g->beta[i] = -a * gS[i] - a / (b * b) * sn - a / b * s_tau[i % M];
+    }
+  }
+  return part1 + part2 + part3;
+}
+
+// The recursion form for a window: shared or per-pair decays.
+double recursion_eval(const Window& win, const Params& p, Grad* g, Scale* sc = nullptr) {
+  if (p.shared && !g_pairwise_shared) return recursion_window_shared(win, p, g, sc);
+  return recursion_window(win, p, g, sc);
+}
+
 void store_grad(const Grad& g, int M, int beta_mode, int64_t w, double* g_mu,
                 double* g_alpha, double* g_beta) {
   const int MM = M * M;
@@ -324,7 +416,7 @@ int eval_batch(const int64_t* offsets, const double* t, const int32_t* dim,
     Params p = load_params(M, beta_mode, mu, alpha, beta, w);
     Grad g;
     ll[w] = kBrute ? brute_window(win, p, want_grad ? &g : nullptr)
-                   : recursion_window(win, p, want_grad ? &g : nullptr);
+                   : recursion_eval(win, p, want_grad ? &g : nullptr);
     if (want_grad) store_grad(g, M, beta_mode, w, g_mu, g_alpha, g_beta);
   });
   return 0;
@@ -574,8 +666,9 @@ int mdhp_oracle_fit(const int64_t* offsets, const double* t, const int32_t* dim,
         p.alpha.assign(x.begin() + M, x.begin() + M + MM);
         p.beta.resize(MM);
         for (int i = 0; i < MM; ++i) p.beta[i] = beta_mode == 0 ? x[M + MM] : x[M + MM + i];
+        p.shared = beta_mode == 0;
         Grad g;
-        const double l = recursion_window(win, p, &g);
+        const double l = recursion_eval(win, p, &g);
         std::copy(g.mu.begin(), g.mu.end(), gout.begin());
         std::copy(g.alpha.begin(), g.alpha.end(), gout.begin() + M);
         if (beta_mode == 0) {
@@ -609,8 +702,9 @@ int mdhp_oracle_fit(const int64_t* offsets, const double* t, const int32_t* dim,
       p.alpha.assign(th.begin() + M, th.begin() + M + MM);
       p.beta.resize(MM);
       for (int i = 0; i < MM; ++i) p.beta[i] = beta_mode == 0 ? th[M + MM] : th[M + MM + i];
+      p.shared = beta_mode == 0;
       Grad g;
-      const double l = recursion_window(win, p, &g);
+      const double l = recursion_eval(win, p, &g);
       bool finite = std::isfinite(l);
       std::copy(g.mu.begin(), g.mu.end(), gv.begin());
       std::copy(g.alpha.begin(), g.alpha.end(), gv.begin() + M);
@@ -687,13 +781,17 @@ int mdhp_oracle_scales(const int64_t* offsets, const double* t, const int32_t* d
     Window win{t + offsets[w], dim + offsets[w], offsets[w + 1] - offsets[w], T[w]};
     Params p = load_params(M, beta_mode, mu, alpha, beta, w);
     Scale sc;
-    recursion_window(win, p, nullptr, &sc);
+    recursion_eval(win, p, nullptr, &sc);
     ll_scale[w] = sc.ll;
     Grad g{sc.mu, sc.alpha, sc.beta};
     store_grad(g, M, beta_mode, w, s_mu, s_alpha, s_beta);
   });
   return 0;
 }
+
+// Non-zero: the shared mode runs the per-pair recursion with the decay
+// copied into every pair (the cross-check of the two forms).
+void mdhp_oracle_set_pairwise_shared(int32_t on) { g_pairwise_shared = on != 0; }
 
 // Threads the pool uses when nthreads <= 0 is passed.
 int mdhp_oracle_default_threads(void) {

@@ -24,11 +24,12 @@ EXPORTS = (
     "mdhp_surrogate_backward", "mdhp_surrogate_get_gradients", "mdhp_surrogate_adam",
     "mdhp_surrogate_train_step", "mdhp_warm_start", "mdhp_cold_start", "mdhp_plan_autotune",
     "mdhp_plan_set_schedule", "mdhp_plan_schedule", "mdhp_plan_create_scheduled",
+    "mdhp_surrogate_save", "mdhp_surrogate_load",
 )
 
 MDHP_OK = 0
 STATUS_NAMES = {0: "MDHP_OK", -1: "MDHP_E_INVAL", -2: "MDHP_E_UNSORTED", -3: "MDHP_E_DOMAIN",
-                -4: "MDHP_E_PARAM", -5: "MDHP_E_NOMEM", -6: "MDHP_E_HIP"}
+                -4: "MDHP_E_PARAM", -5: "MDHP_E_NOMEM", -6: "MDHP_E_HIP", -7: "MDHP_E_IO"}
 BETA_SHARED, BETA_PAIR = 0, 1
 OPT_PGD, OPT_PADAM, OPT_LBFGS = 0, 1, 2
 FIT_CONVERGED, FIT_MAX_STEPS, FIT_NONFINITE, FIT_STALLED = 0, 1, 2, 3
@@ -49,7 +50,8 @@ class MdhpFitOpts(ctypes.Structure):
                 ("lr", ctypes.c_double), ("ll_tol", ctypes.c_double),
                 ("mu_floor_rel", ctypes.c_double), ("beta_floor_rel", ctypes.c_double),
                 ("adam_b1", ctypes.c_double), ("adam_b2", ctypes.c_double),
-                ("adam_eps", ctypes.c_double)]
+                ("adam_eps", ctypes.c_double), ("check_params", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class MdhpTuneResult(ctypes.Structure):
@@ -114,6 +116,8 @@ def load() -> ctypes.CDLL:
     lib.mdhp_surrogate_train_step.argtypes = [P, P, I32, P, ctypes.c_float, P, P]
     lib.mdhp_warm_start.argtypes = [P, P, P, P, ctypes.POINTER(MdhpFitOpts), P, P, P, P, P, P,
                                     P, P]
+    lib.mdhp_surrogate_save.argtypes = [P, ctypes.c_char_p, P, I64, P]
+    lib.mdhp_surrogate_load.argtypes = [P, ctypes.c_char_p, P, I64, ctypes.POINTER(I64), P]
     lib.mdhp_status_string.argtypes = [I32]
     lib.mdhp_status_string.restype = ctypes.c_char_p
     lib.mdhp_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
@@ -123,7 +127,8 @@ def load() -> ctypes.CDLL:
                  "mdhp_surrogate_get_gradients", "mdhp_surrogate_forward",
                  "mdhp_surrogate_get_hidden", "mdhp_surrogate_backward", "mdhp_surrogate_adam",
                  "mdhp_surrogate_train_step", "mdhp_warm_start", "mdhp_cold_start",
-                 "mdhp_plan_autotune", "mdhp_plan_set_schedule"):
+                 "mdhp_plan_autotune", "mdhp_plan_set_schedule", "mdhp_surrogate_save",
+                 "mdhp_surrogate_load"):
         getattr(lib, name).restype = I32
     _lib = lib
     return lib

@@ -54,12 +54,14 @@ class FitOptions:
     adam_b1: float = 0.9
     adam_b2: float = 0.999
     adam_eps: float = 1e-8
+    check_params: bool = False
 
     def to_c(self) -> _lib.MdhpFitOpts:
         return _lib.MdhpFitOpts(int(self.max_steps), int(self.optimizer), int(bool(self.fix_beta)),
                                 int(self.history), float(self.lr), float(self.ll_tol), float(self.mu_floor_rel),
                                 float(self.beta_floor_rel), float(self.adam_b1),
-                                float(self.adam_b2), float(self.adam_eps))
+                                float(self.adam_b2), float(self.adam_eps),
+                                int(bool(self.check_params)), 0)
 
 
 def mdhp_status_string(status: int) -> str:

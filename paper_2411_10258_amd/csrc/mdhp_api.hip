@@ -240,6 +240,7 @@ const char* mdhp_status_string(mdhp_status s) {
     case MDHP_E_PARAM: return "invalid parameter value";
     case MDHP_E_NOMEM: return "device allocation failed";
     case MDHP_E_HIP: return "HIP runtime error";
+    case MDHP_E_IO: return "checkpoint file error";
     default: return "unknown status";
   }
 }
@@ -454,6 +455,14 @@ mdhp_status mdhp_fit_batch(mdhp_plan* p, const mdhp_fit_opts* o, float* mu, floa
     return fail(MDHP_E_INVAL, "fit_batch: invalid options");
   if (o->optimizer == MDHP_OPT_LBFGS && p->beta_mode != MDHP_BETA_SHARED)
     return fail(MDHP_E_INVAL, "fit_batch: L-BFGS needs one decay per window");
+  if (o->check_params && p->W > 0) {
+    const mdhp_status st = mdhp_check_params(p, mu, alpha, beta, stream);
+    if (st != MDHP_OK)
+      return st == MDHP_E_PARAM
+                 ? fail(MDHP_E_PARAM, "fit_batch: initial mu <= 0, alpha < 0, beta <= 0 or "
+                                      "non-finite")
+                 : st;
+  }
   FitParams fp{o->max_steps,  o->optimizer,      o->fix_beta, o->history > 0 ? o->history : 8,
                o->lr,         o->ll_tol,         o->mu_floor_rel, o->beta_floor_rel,
                o->adam_b1,    o->adam_b2,        o->adam_eps};

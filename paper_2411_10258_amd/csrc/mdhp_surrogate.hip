@@ -9,6 +9,7 @@
 // prediction is used).
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -284,6 +285,14 @@ struct mdhp_surrogate {
 
 namespace {
 constexpr uint32_t kSurrogateMagic = 0x5355524fu;
+// Checkpoint header (see mdhp_surrogate_save); 48 bytes, no padding.
+constexpr char kCheckpointMagic[8] = {'M', 'D', 'H', 'P', 'S', 'U', 'R', '1'};
+struct CheckpointHeader {
+  char magic[8];
+  int32_t version, in_dim, hidden, out_dim;
+  int64_t n_params, step, n_extra;
+};
+static_assert(sizeof(CheckpointHeader) == 48, "checkpoint header layout");
 bool sur_ok(const mdhp_surrogate* s) { return s && s->magic == kSurrogateMagic; }
 void free_sur(mdhp_surrogate* s) {
   for (void* p : {(void*)s->w, (void*)s->g, (void*)s->m1, (void*)s->m2, (void*)s->wb,
@@ -511,6 +520,80 @@ mdhp_status mdhp_surrogate_adam(mdhp_surrogate* s, float lr, float b1, float b2,
                      s->w, s->g, s->m1, s->m2, s->wb, s->n_params, lr, b1, b2, eps, bc1, bc2);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? MDHP_OK : mdhp_hip_fail(e, "surrogate_adam");
+}
+
+mdhp_status mdhp_surrogate_save(mdhp_surrogate* s, const char* path, const float* extra,
+                                int64_t n_extra, void* stream) {
+  if (!sur_ok(s) || !path || n_extra < 0 || (n_extra > 0 && !extra))
+    return mdhp_fail(MDHP_E_INVAL, "surrogate_save: invalid argument");
+  const int64_t n = s->n_params;
+  std::vector<float> host((size_t)n * 3);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(host.data(), s->w, n * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(host.data() + n, s->m1, n * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host.data() + 2 * n, s->m2, n * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return mdhp_hip_fail(e, "surrogate_save");
+  CheckpointHeader h;
+  std::memcpy(h.magic, kCheckpointMagic, 8);
+  h.version = 1;
+  h.in_dim = s->in_dim;
+  h.hidden = s->hidden;
+  h.out_dim = s->out_dim;
+  h.n_params = n;
+  h.step = s->step;
+  h.n_extra = n_extra;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return mdhp_fail(MDHP_E_IO, std::string("surrogate_save: cannot open ") + path);
+  bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 &&
+            std::fwrite(host.data(), 4, host.size(), f) == host.size() &&
+            (n_extra == 0 || std::fwrite(extra, 4, (size_t)n_extra, f) == (size_t)n_extra);
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return mdhp_fail(MDHP_E_IO, std::string("surrogate_save: write failed: ") + path);
+  return MDHP_OK;
+}
+
+mdhp_status mdhp_surrogate_load(mdhp_surrogate* s, const char* path, float* extra,
+                                int64_t extra_cap, int64_t* n_extra, void* stream) {
+  if (!sur_ok(s) || !path || extra_cap < 0)
+    return mdhp_fail(MDHP_E_INVAL, "surrogate_load: invalid argument");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return mdhp_fail(MDHP_E_IO, std::string("surrogate_load: cannot open ") + path);
+  CheckpointHeader h;
+  if (std::fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, kCheckpointMagic, 8) != 0 ||
+      h.version != 1 || h.n_extra < 0) {
+    std::fclose(f);
+    return mdhp_fail(MDHP_E_IO, std::string("surrogate_load: not a surrogate checkpoint: ") + path);
+  }
+  if (h.in_dim != s->in_dim || h.hidden != s->hidden || h.out_dim != s->out_dim ||
+      h.n_params != s->n_params) {
+    std::fclose(f);
+    return mdhp_fail(MDHP_E_INVAL, "surrogate_load: the checkpoint's network has another shape");
+  }
+  const int64_t n = s->n_params;
+  std::vector<float> host((size_t)n * 3);
+  std::vector<float> ext((size_t)h.n_extra);
+  const bool ok = std::fread(host.data(), 4, host.size(), f) == host.size() &&
+                  (h.n_extra == 0 || std::fread(ext.data(), 4, ext.size(), f) == ext.size());
+  std::fclose(f);
+  if (!ok) return mdhp_fail(MDHP_E_IO, std::string("surrogate_load: truncated file: ") + path);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(s->w, host.data(), n * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(s->m1, host.data() + n, n * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->m2, host.data() + 2 * n, n * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, st, s->w, s->wb, n);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return mdhp_hip_fail(e, "surrogate_load");
+  s->step = h.step;
+  if (n_extra) *n_extra = h.n_extra;
+  if (extra && h.n_extra > 0)
+    std::memcpy(extra, ext.data(), (size_t)std::min<int64_t>(extra_cap, h.n_extra) * 4);
+  return MDHP_OK;
 }
 
 mdhp_status mdhp_surrogate_train_step(mdhp_surrogate* s, const uint16_t* x, int32_t B,

@@ -16,6 +16,7 @@ Inputs: log1p(count * bins / T) for 64 equal bins per dimension.
 from __future__ import annotations
 
 import ctypes
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -137,6 +138,30 @@ class Surrogate:
         _lib.check(_lib.load().mdhp_surrogate_get_hidden(self._h(), int(B), _ptr(h1), _ptr(h2),
                                                          ctypes.c_void_p(_stream())))
         return h1, h2
+
+    def save(self, path: str) -> None:
+        """Checkpoint (mdhp_surrogate_save): weights, Adam moments and step,
+        with the target normalisation (mean, std) as the file's extra data."""
+        extra = (np.zeros(0, np.float32) if self.stats is None else
+                 np.concatenate([self.stats.mean, self.stats.std]).astype(np.float32))
+        _lib.check(_lib.load().mdhp_surrogate_save(
+            self._h(), os.fsencode(path), extra.ctypes.data_as(ctypes.c_void_p) if extra.size
+            else None, int(extra.size), ctypes.c_void_p(_stream())))
+
+    def load(self, path: str) -> None:
+        """Restores a checkpoint written by save() for a network of this shape."""
+        cap = 2 * self.out_dim
+        extra = np.zeros(cap, np.float32)
+        n = ctypes.c_int64(0)
+        _lib.check(_lib.load().mdhp_surrogate_load(self._h(), os.fsencode(path),
+                                                   extra.ctypes.data_as(ctypes.c_void_p), cap,
+                                                   ctypes.byref(n), ctypes.c_void_p(_stream())))
+        if n.value == cap:
+            self.stats = TargetStats(extra[:self.out_dim].copy(), extra[self.out_dim:].copy())
+        elif n.value == 0:
+            self.stats = None
+        else:
+            raise ValueError(f"{path}: {n.value} extra values, expected 0 or {cap}")
 
     def forward(self, x: torch.Tensor) -> torch.Tensor:
         """[N, out_dim] float32 predictions for BF16 features x [N, in_dim]."""

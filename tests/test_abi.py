@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts():
     from paper_2411_10258_amd import _lib
     import oracle
-    assert ctypes.sizeof(_lib.MdhpFitOpts) == 72
+    assert ctypes.sizeof(_lib.MdhpFitOpts) == 80
     assert ctypes.sizeof(_lib.MdhpBatch) == 48
     assert len(oracle.FitOpts().pack()) == 72
 
@@ -42,7 +42,7 @@ def test_struct_layouts():
 def test_host_error_paths():
     from paper_2411_10258_amd import _lib
     lib = _lib.load()
-    for s in range(-6, 1):
+    for s in range(-7, 1):
         assert lib.mdhp_status_string(s)
     out = ctypes.c_void_p()
     assert lib.mdhp_plan_create(None, 4, 0, None, ctypes.byref(out)) == -1

@@ -60,16 +60,15 @@ def test_graph_warm_padam_m16(gpu, synth_lib):
     net.close()
 
 
-def test_graph_cold_pgd_wide(gpu, synth_lib):
-    # M = 20: pass 1 and Gmu use LDS adds whose order varies from run to run,
-    # so two runs differ by rounding.  A fixed number of projected gradient
-    # steps (no line search, no stop) keeps those differences at rounding
-    # level, so replays and the eager run agree to 1e-6 of max(|ll|, N).
-    b = synth_lib.random_small(5, 16, 20, 0, n_lo=200, n_hi=3000)
-    print(f"[graph] cold PGD M=20 W={b.W}", flush=True)
+@pytest.mark.parametrize("M", [20, 64])
+def test_graph_cold_lbfgs_wide(gpu, synth_lib, M):
+    # The lane-per-dimension kernels (16 < M <= 64) sum in a fixed order, so
+    # replays of a whole L-BFGS fit (whose line search and stop rule would
+    # turn any rounding difference into another trajectory) match the eager
+    # run bit for bit.
+    b = synth_lib.random_small(5, 16, M, 0, n_lo=200, n_hi=3000)
+    print(f"[graph] cold L-BFGS M={M} W={b.W}", flush=True)
     plan = gpu.Plan(b.offsets, b.t, b.dim, b.T, b.M, 0)
-    opts = gpu.FitOptions(max_steps=20, optimizer=gpu.OPT_PGD, lr=1e-2, ll_tol=0.0)
-    from paper_2411_10258_amd import graph
-    ll = graph.fit_pipeline(plan, opts)[3].cpu().numpy()
-    _replays(gpu, plan, opts, exact=False, scale=np.maximum(np.abs(ll), b.counts), tol=1e-6)
+    opts = gpu.FitOptions(max_steps=60, optimizer=gpu.OPT_LBFGS, ll_tol=1e-7, history=5)
+    _replays(gpu, plan, opts)
     plan.close()

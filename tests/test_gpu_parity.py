@@ -278,3 +278,25 @@ def test_cold_start_matches_its_definition(gpu, synth_lib, beta_mode, M):
     assert np.all(be.cpu().numpy() == 1.0)
     assert tuple(be.shape) == ((b.W,) if beta_mode == 0 else (b.W, M, M))
     plan.close()
+
+
+def test_fit_entry_parameter_check(gpu, synth_lib):
+    """opts.check_params: invalid initial values are refused with E_PARAM
+    before any fitting; valid ones fit as without the check."""
+    import torch
+    b = synth_lib.random_small(8, 4, 20, 0, n_lo=10, n_hi=200)
+    plan = gpu.Plan(b.offsets, b.t, b.dim, b.T, b.M, 0)
+    mu = torch.full((b.W, b.M), 0.5)
+    al = torch.full((b.W, b.M, b.M), 0.01)
+    be = torch.ones(b.W)
+    print("[parity] fit entry check", flush=True)
+    o = gpu.FitOptions(max_steps=3, optimizer=gpu.OPT_PGD, ll_tol=0.0, check_params=True)
+    ref = plan.fit(mu, al, be, gpu.FitOptions(max_steps=3, optimizer=gpu.OPT_PGD, ll_tol=0.0))
+    out = plan.fit(mu, al, be, o)
+    for x, y in zip(ref, out):
+        assert torch.equal(x, y)
+    for bad in ((mu * 0, al, be), (mu, -al, be), (mu, al, be * float("nan"))):
+        with pytest.raises(gpu.MdhpError) as e:
+            plan.fit(*bad, o)
+        assert e.value.status == -4
+    plan.close()

@@ -136,3 +136,51 @@ def test_warm_start_falls_back_to_cold(gpu, oracle_lib, synth_lib):
     assert np.allclose(alpha.cpu().numpy()[~bad], a_true[~bad], rtol=1e-4)
     plan.close()
     net.close()
+
+
+def test_checkpoint_round_trip(gpu, tmp_path):
+    """save/load restores weights, both Adam moments and the step: the next
+    training step of the restored network is bitwise the original's."""
+    import torch
+    from paper_2411_10258_amd import _lib, surrogate
+    rng = np.random.default_rng(4)
+    a = _net(gpu, seed=5, max_batch=64)
+    x = _bf16_tensor(np.abs(rng.standard_normal((64, a.in_dim))))
+    t = torch.from_numpy(rng.standard_normal((64, a.out_dim)).astype(np.float32)).cuda()
+    print("[surrogate] checkpoint", flush=True)
+    for _ in range(3):
+        a.train_step(x, t, 1e-3)
+    a.stats = surrogate.TargetStats(rng.standard_normal(a.out_dim).astype(np.float32),
+                                    rng.uniform(0.5, 2, a.out_dim).astype(np.float32))
+    path = str(tmp_path / "net.ckpt")
+    a.save(path)
+    b = _net(gpu, seed=99, max_batch=64)
+    assert not torch.equal(a.get_weights(), b.get_weights())
+    b.load(path)
+    assert torch.equal(a.get_weights(), b.get_weights())
+    assert np.array_equal(a.stats.mean, b.stats.mean) and np.array_equal(a.stats.std, b.stats.std)
+    la = a.train_step(x, t, 1e-3).item()
+    lb = b.train_step(x, t, 1e-3).item()
+    torch.cuda.synchronize()
+    assert la == lb
+    assert torch.equal(a.get_weights(), b.get_weights())
+    # Another shape, a foreign file, a truncated file, a missing file.
+    c = surrogate.Surrogate(16, hidden=256, max_batch=8, seed=1)
+    with pytest.raises(gpu.MdhpError) as e:
+        c.load(path)
+    assert e.value.status == -1
+    bad = tmp_path / "foreign.bin"
+    bad.write_bytes(b"not a checkpoint" * 8)
+    with pytest.raises(gpu.MdhpError) as e:
+        b.load(str(bad))
+    assert e.value.status == -7
+    cut = tmp_path / "cut.ckpt"
+    cut.write_bytes(open(path, "rb").read()[:1000])
+    with pytest.raises(gpu.MdhpError) as e:
+        b.load(str(cut))
+    assert e.value.status == -7
+    with pytest.raises(gpu.MdhpError) as e:
+        b.load(str(tmp_path / "missing.ckpt"))
+    assert e.value.status == -7
+    for n in (a, b, c):
+        n.close()

@@ -357,3 +357,27 @@ def test_lbfgs_fit_reaches_lbfgsb_optimum(oracle_lib, synth_lib):
                        options=dict(maxiter=5000, ftol=1e-16, gtol=1e-12))
         assert r[3][0] == pytest.approx(-ref.fun, rel=1e-8, abs=1e-8)
         assert r[6][0] >= r[4][0] + 1
+
+
+# ---------------------------------------------------------------------------
+# The shared-decay recursion (O(N M)) against the per-pair recursion with the
+# decay copied into every pair (O(N M^2)): same ll, gradient, scales, fits.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("grid", [0.0, 0.2])
+def test_shared_recursion_matches_pairwise_form(oracle_lib, synth_lib, grid):
+    b = synth_lib.random_small(41, 12, 6, 0, n_lo=0, n_hi=400, tie_grid=grid)
+    args = (b.offsets, b.t, b.dim, b.T, b.M, b.mu, b.alpha, b.beta, 0)
+    fo = oracle_lib.FitOpts(max_steps=15, optimizer=2, ll_tol=0.0, history=4)
+    res = []
+    try:
+        for pairwise in (False, True):
+            oracle_lib.set_pairwise_shared(pairwise)
+            res.append((oracle_lib.grad(*args), oracle_lib.scales(*args),
+                        oracle_lib.fit(*args[:5], b.mu, b.alpha, b.beta, fo)))
+    finally:
+        oracle_lib.set_pairwise_shared(False)
+    (g1, s1, f1), (g2, s2, f2) = res
+    for x, y in zip(g1 + s1, g2 + s2):
+        np.testing.assert_allclose(x, y, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(f1[3], f2[3], rtol=1e-10)
