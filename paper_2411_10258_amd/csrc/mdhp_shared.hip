@@ -27,9 +27,13 @@
 // recursion runs B = 8 events, then one reduce-scatter across the group's
 // lanes (lane swaps 32 and 16 apart, DPP within rows) turns the B partial
 // dot products alpha_{d_i n} R_n(i) into intensities, P / B lanes per
-// event; the reciprocals return through LDS and G_R[d_i][n] += R_n(i) /
-// lambda_i is one LDS add per event and lane (lane n owns column n, so the
-// adds of one event never collide).  The pending one-hot row [d_i = n] is
+// event.  At P = 64 each wave keeps its chunk's G_R in registers (lane n:
+// column n) and G_R[d_i][n] += R_n(i) / lambda_i is one FMA on the register
+// of row d_i, with 1 / lambda_i read from its lane as a scalar; at P = 32
+// the reciprocals return through LDS and the row update is one LDS add per
+// event and lane (lane n owns column n, so the adds of one event never
+// collide).  A block of events without equal times skips the
+// pending-count select of the recursion.  The pending one-hot row [d_i = n] is
 // read from LDS next to alpha_{d_i n}.  LDS sums that several lanes add to
 // (chunk carries, G_R at P = 32, Gmu) have one copy per group or wavefront:
 // adds from different wavefronts never meet, and the copies are summed in a
@@ -108,6 +112,20 @@ __device__ __forceinline__ void swap_add16(float& a, float b) {
                                                   __builtin_bit_cast(unsigned, b), false, false);
   const unsigned x = r[0], y = r[1];  // (a bit cast of r[i] itself reads element 0)
   a = __uint_as_float(x) + __uint_as_float(y);
+}
+// G_R row `row` += w * r for the wave's 64 x 64 register accumulator:
+// lane n holds column n, rows 0..31 in v40..v71 and 32..63 in v72..v103
+// (fixed registers, so that one indexed FMA reaches any row: the row is
+// uniform, one event's target).  The index mode applies to the FMA's
+// accumulator operand and destination only.
+__device__ __forceinline__ void gr_row_fma(f32x32& lo, f32x32& hi, int row, float w, float r) {
+  int m0;  // the index mode writes M0
+  asm volatile(
+      "s_set_gpr_idx_on %3, gpr_idx(SRC2,DST)\n\t"
+      "v_fma_f32 v40, %4, %5, v40\n\t"
+      "s_set_gpr_idx_off"
+      : "+{v[40:71]}"(lo), "+{v[72:103]}"(hi), "={m0}"(m0)
+      : "s"(row), "s"(w), "v"(r));
 }
 // Keeps v[e + h] where the lane bit is set (else v[e]) and adds the partner's.
 template <int CTRL, int H>
@@ -349,32 +367,55 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
       wave_sync();  // the previous block's reads are done
       meta[lane] = make_float4(__expf(-beta * dt_l), dt_l, __builtin_bit_cast(float, d_l),
                                d_l < P ? sh.mu[d_l] : -1.f);
+      // A block without equal times (the usual case for continuous times)
+      // needs no pending-count select: R(j) is the decayed inclusive state.
+      const bool tie_free = __builtin_amdgcn_ballot_w64(d_l < P && !(dt_l > 0.f)) == 0;
       wave_sync();
 #pragma unroll 1
       for (int sb = 0; sb < P; sb += B) {
         float L[B], AS[B], Rj[B];
         int Dj[B];
-        static_for<B>([&](auto J) {
-          constexpr int j = decltype(J)::value;
-          const float4 m = meta[sb + j];
-          const float a = m.x, dt = m.y;
-          const int d = __builtin_bit_cast(int, m.z);
-          const float x = a * Rin;  // decayed over the gap; R moves only when time does
-          S = fmaf(a, S, dt * x);
-          R = dt > 0.f ? x : R;
-          const float2 ao = sh.ao[d * P + lane];
-          L[j] = ao.x * R;
-          AS[j] = ao.x * S;
-          Rj[j] = R;
-          Dj[j] = d;
-          Rin = x + ao.y;  // the event itself is pending until time moves on
-        });
+        auto recur = [&](auto tf) {
+          constexpr bool kTieFree = decltype(tf)::value;
+          static_for<B>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            const float4 m = meta[sb + j];
+            const float a = m.x, dt = m.y;
+            const int d = __builtin_bit_cast(int, m.z);
+            const float x = a * Rin;  // decayed over the gap; R moves only when time does
+            S = fmaf(a, S, dt * x);
+            if constexpr (kTieFree) R = x;
+            else R = dt > 0.f ? x : R;
+            const float2 ao = sh.ao[d * P + lane];
+            L[j] = ao.x * R;
+            AS[j] = ao.x * S;
+            Rj[j] = R;
+            Dj[j] = d;
+            Rin = x + ao.y;  // the event itself is pending until time moves on
+          });
+        };
+        if (tie_free) recur(std::true_type{});
+        else recur(std::false_type{});
         float lam = group_reduce_scatter<P, B>(L);
         const float4 me = meta[sb + ev_l];
         const bool valid = me.w >= 0.f;
         lam += me.w;
         llp += (lead && valid) ? __logf(lam) : 0.f;
-        if constexpr (GRAD) {
+        if constexpr (kRegGR) {
+          // 1 / lambda of event j is in lane j << SH; read as a scalar, it
+          // scales R(j) into row d_j of the wave's G_R registers (one
+          // indexed FMA) and S into the decay gradient.
+          const float w = valid ? __builtin_amdgcn_rcpf(lam) : 0.f;
+          if (lead && valid) atomicAdd(&gmuL[__builtin_bit_cast(int, me.z)], w);
+          static_for<B>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            const float wj = __builtin_bit_cast(
+                float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, w), j << SH));
+            const int dj = __builtin_amdgcn_readfirstlane(Dj[j]) & (P - 1);
+            gr_row_fma(gacc0, gacc1, dj, wj, Rj[j]);
+            gbp = fmaf(wj, AS[j], gbp);
+          });
+        } else if constexpr (GRAD) {
           const float w = valid ? __builtin_amdgcn_rcpf(lam) : 0.f;
           if (lead) {
             wb[ev_l] = w;
@@ -392,17 +433,7 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
           }
 #pragma unroll
           for (int j = 0; j < B; ++j) {
-            const float x = wv[j] * Rj[j];
-            if constexpr (kRegGR) {
-              // Row d of the wave's G_R registers (d is uniform: one event).
-              const int d = __builtin_amdgcn_readfirstlane(Dj[j]);
-              const int dl = d & 31;
-              const bool hi = d >= 32;
-              gacc0[dl] += hi ? 0.f : x;
-              gacc1[dl] += hi ? x : 0.f;
-            } else {
-              atomicAdd(&gRc[Dj[j] * P + lane], x);
-            }
+            atomicAdd(&gRc[Dj[j] * P + lane], wv[j] * Rj[j]);
             gbp = fmaf(wv[j], AS[j], gbp);
           }
           wave_sync();  // wb is rewritten by the next events
@@ -646,7 +677,7 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_eva
 
 // Persistent projected-gradient fit (see mdhp_fit_opts for the rule).
 template <int P, int SB>
-__global__ __launch_bounds__(kBlock, (P == 32 ? 2 : kMinBlocks)) void shared_fit_kernel(Events ev, int M, FitParams o,
+__global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_fit_kernel(Events ev, int M, FitParams o,
                                                             float* mu, float* alpha, float* beta,
                                                             double* ll, int* steps, int* status,
                                                             int* evals_out, int* counter) {
@@ -786,7 +817,7 @@ __device__ __forceinline__ double block_max_abs(double v, double* scratch) {
 // reads and writes; the scalars of the two-loop recursion come from block
 // reductions.
 template <int P, int SB>
-__global__ __launch_bounds__(kBlock, (P == 32 ? 2 : kMinBlocks)) void shared_lbfgs_kernel(Events ev, int M, FitParams o,
+__global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_lbfgs_kernel(Events ev, int M, FitParams o,
                                                               float* mu, float* alpha,
                                                               float* beta, double* ll,
                                                               int* steps, int* status,
