@@ -206,6 +206,32 @@ mdhp_status mdhp_fit_batch(mdhp_plan* plan, const mdhp_fit_opts* opts, float* mu
  * memory owned by the caller.  Enqueued on stream. */
 mdhp_status mdhp_cold_start(mdhp_plan* plan, float* mu, float* alpha, float* beta, void* stream);
 
+/* Allocation-free likelihood and gradient, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation.  No plan: the batch (device pointers, as for
+ * mdhp_plan_create, one decay per window: mu [W][M], alpha [W][M][M],
+ * beta [W]) is prepared and evaluated on `stream` in one asynchronous call,
+ * with the same Eq. (5) likelihood and gradient as mdhp_grad (lane-per-
+ * dimension kernels for every M in [1, 64], windows in their given order).
+ * The call allocates nothing: the prepared events live in one fixed device
+ * array of the library (MDHP_STATIC_BYTES, each GPU it runs on holds its
+ * own copy until the process ends), whose address is looked up once per
+ * device on its first call there.  Every call on a GPU shares that array:
+ * calls that overlap on one GPU (other streams, other host threads) race
+ * and must be serialised by the caller.  Limits: W <= MDHP_STATIC_MAX_WINDOWS
+ * and n_events <= MDHP_STATIC_MAX_EVENTS (MDHP_E_INVAL beyond).  g_mu,
+ * g_alpha, g_beta: all three (gradient of ll) or all NULL (likelihood only).
+ * The host reads nothing back, so events are validated on the device: a
+ * window whose events are unsorted or out of range, or whose offsets are
+ * inconsistent, gets ll = NaN (and NaN gradients); offsets are clamped to
+ * [0, n_events] before any event is read. */
+#define MDHP_STATIC_MAX_EVENTS 4194304
+#define MDHP_STATIC_MAX_WINDOWS 65536
+#define MDHP_STATIC_BYTES 56623616
+mdhp_status mdhp_grad_static(const mdhp_batch* batch, int32_t M, const float* mu,
+                             const float* alpha, const float* beta, double* ll, float* g_mu,
+                             float* g_alpha, float* g_beta, void* stream);
+
 /* Checks parameter values on the device (mu > 0, alpha >= 0, beta > 0, all
  * finite) and returns MDHP_E_PARAM if any window violates them.
  * Synchronous on `stream`. */

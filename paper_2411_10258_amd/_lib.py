@@ -24,7 +24,7 @@ EXPORTS = (
     "mdhp_surrogate_backward", "mdhp_surrogate_get_gradients", "mdhp_surrogate_adam",
     "mdhp_surrogate_train_step", "mdhp_warm_start", "mdhp_cold_start", "mdhp_plan_autotune",
     "mdhp_plan_set_schedule", "mdhp_plan_schedule", "mdhp_plan_create_scheduled",
-    "mdhp_surrogate_save", "mdhp_surrogate_load",
+    "mdhp_surrogate_save", "mdhp_surrogate_load", "mdhp_grad_static",
 )
 
 MDHP_OK = 0
@@ -118,6 +118,7 @@ def load() -> ctypes.CDLL:
                                     P, P]
     lib.mdhp_surrogate_save.argtypes = [P, ctypes.c_char_p, P, I64, P]
     lib.mdhp_surrogate_load.argtypes = [P, ctypes.c_char_p, P, I64, ctypes.POINTER(I64), P]
+    lib.mdhp_grad_static.argtypes = [ctypes.POINTER(MdhpBatch), I32, P, P, P, P, P, P, P, P]
     lib.mdhp_status_string.argtypes = [I32]
     lib.mdhp_status_string.restype = ctypes.c_char_p
     lib.mdhp_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
@@ -128,7 +129,7 @@ def load() -> ctypes.CDLL:
                  "mdhp_surrogate_get_hidden", "mdhp_surrogate_backward", "mdhp_surrogate_adam",
                  "mdhp_surrogate_train_step", "mdhp_warm_start", "mdhp_cold_start",
                  "mdhp_plan_autotune", "mdhp_plan_set_schedule", "mdhp_surrogate_save",
-                 "mdhp_surrogate_load"):
+                 "mdhp_surrogate_load", "mdhp_grad_static"):
         getattr(lib, name).restype = I32
     _lib = lib
     return lib

@@ -18,7 +18,7 @@ from ._lib import (BETA_PAIR, BETA_SHARED, FIT_CONVERGED, FIT_MAX_STEPS, FIT_NON
 
 __all__ = ["Plan", "FitOptions", "mdhp_plan_create", "mdhp_plan_destroy", "mdhp_loglik",
            "mdhp_grad", "mdhp_fit_batch", "mdhp_check_params", "mdhp_cold_start", "mdhp_status_string",
-           "mdhp_plan_autotune", "mdhp_plan_set_schedule", "mdhp_plan_schedule",
+           "mdhp_plan_autotune", "mdhp_plan_set_schedule", "mdhp_plan_schedule", "mdhp_grad_static",
            "BETA_SHARED", "BETA_PAIR", "OPT_PGD", "OPT_PADAM", "OPT_LBFGS", "FIT_CONVERGED",
            "FIT_MAX_STEPS", "FIT_NONFINITE", "FIT_STALLED", "MdhpError"]
 
@@ -110,6 +110,20 @@ def mdhp_grad(handle, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, stream=None) -
     _lib.check(_lib.load().mdhp_grad(ctypes.c_void_p(handle), _ptr(mu), _ptr(alpha), _ptr(beta),
                                      _ptr(ll), _ptr(g_mu), _ptr(g_alpha), _ptr(g_beta),
                                      ctypes.c_void_p(_stream(stream))))
+
+
+def mdhp_grad_static(batch, M: int, mu, alpha, beta, ll, g_mu=None, g_alpha=None, g_beta=None,
+                     stream=None) -> None:
+    """The allocation-free likelihood (and gradient): batch = (offsets, t, dim,
+    T) as device tensors of the mdhp_batch types (int64, float64, int32,
+    float64); every other argument is a device tensor as for mdhp_grad."""
+    offsets, t, dim, T = batch
+    b = _lib.MdhpBatch(T.numel(), t.numel(), offsets.data_ptr(), t.data_ptr(), dim.data_ptr(),
+                       T.data_ptr())
+    grads = (g_mu, g_alpha, g_beta)
+    _lib.check(_lib.load().mdhp_grad_static(
+        ctypes.byref(b), int(M), _ptr(mu), _ptr(alpha), _ptr(beta), _ptr(ll),
+        *(None if g is None else _ptr(g) for g in grads), ctypes.c_void_p(_stream(stream))))
 
 
 def mdhp_fit_batch(handle, opts: FitOptions, mu, alpha, beta, ll, steps, status, evals=None,

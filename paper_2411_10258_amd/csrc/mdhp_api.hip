@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -68,6 +69,18 @@ constexpr int kErrUnsorted = 1, kErrDomain = 2, kErrParam = 4;
 mdhp_status fail(mdhp_status s, const std::string& msg) { return mdhp_fail(s, msg); }
 mdhp_status hip_fail(hipError_t e, const char* where) { return mdhp_hip_fail(e, where); }
 
+// Events [b, e) of window w, clamped to [0, n_events] with e >= b; true if
+// the offsets needed clamping (or offsets[0] != 0, offsets[W] != n_events).
+__device__ __forceinline__ bool window_bounds(const int64_t* __restrict__ offsets, int64_t w,
+                                             int64_t W, int64_t n_events, int64_t& b,
+                                             int64_t& e) {
+  const int64_t ob = offsets[w], oe = offsets[w + 1];
+  b = ob < 0 ? 0 : (ob > n_events ? n_events : ob);
+  e = oe < b ? b : (oe > n_events ? n_events : oe);
+  return b != ob || e != oe || (w == 0 && ob != 0) || (w == W - 1 && oe != n_events) ||
+         e - b > INT32_MAX;
+}
+
 // Sec. IV-B "Stage 1" counterpart: per event, the gap to the previous event
 // of the same window in FP64 (stored FP32; a positive gap never rounds to 0),
 // the distance T - t to the window's end (FP64, stored FP32; the compensator
@@ -85,18 +98,23 @@ __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double
                                float* __restrict__ dt, float* __restrict__ tau,
                                float* __restrict__ gsd, uint8_t* __restrict__ d8,
                                float* __restrict__ end_gap, double* __restrict__ Tc,
-                               int32_t* __restrict__ counts, int* flags) {
+                               int32_t* __restrict__ counts, int* flags, int64_t n_events,
+                               int* __restrict__ wflags) {
   __shared__ int cnt[MDHP_MAX_M];
   for (int64_t w = blockIdx.x; w < W; w += gridDim.x) {
     if (counts) {
       for (int m = threadIdx.x; m < M; m += blockDim.x) cnt[m] = 0;
       __syncthreads();
     }
-    const int64_t b = offsets[w], e = offsets[w + 1];
+    // Offsets checked on the host are in range already; the allocation-free
+    // path cannot check them before launch and relies on this clamp (see
+    // window_bounds) to stay inside the event arrays.
+    int64_t b, e;
+    const bool bad_off = window_bounds(offsets, w, W, n_events, b, e);
     const int64_t L = lane_team(e - b, big_min);
     const int64_t c = (e - b + L - 1) / L;
     const double Tw = T[w];
-    int err = 0;
+    int err = bad_off ? kErrDomain : 0;
     if (!(Tw > 0.0) || !isfinite(Tw)) err |= kErrDomain;
     for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
       const double ti = t[i];
@@ -141,6 +159,11 @@ __global__ void prepare_kernel(const int64_t* __restrict__ offsets, const double
       Tc[w] = Tw;
     }
     if (err) atomicOr(flags, err);
+    if (wflags) {  // per window: every thread's bits
+      if (threadIdx.x == 0) wflags[w] = 0;
+      __syncthreads();
+      if (err) atomicOr(&wflags[w], err);
+    }
   }
 }
 
@@ -353,7 +376,8 @@ mdhp_status build_plan(const mdhp_batch* b, int32_t M, int32_t beta_mode, int64_
       const int grid = (int)std::min<int64_t>(W, 65536);
       hipLaunchKernelGGL(prepare_kernel, dim3(grid), dim3(256), 0, s, b->offsets, b->t, b->dim,
                          b->T, p->lane_major ? p->begin : nullptr, p->big_min, W, M, p->dt,
-                         p->tau, p->gsd, p->d, p->end_gap, p->T, p->counts, p->flags);
+                         p->tau, p->gsd, p->d, p->end_gap, p->T, p->counts, p->flags,
+                         b->n_events, nullptr);
       e = hipGetLastError();
     }
   }
@@ -677,6 +701,156 @@ mdhp_status mdhp_plan_autotune(mdhp_plan* p, const mdhp_batch* b, const mdhp_fit
   if (st != MDHP_OK) return st;
   r->chosen = best;
   return apply_schedule(p, b, v[best], s);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free likelihood and gradient (mdhp_grad_static).  The compact
+// events and per-window arrays of the call live in `scratch`, a fixed device
+// array of this library: one copy per GPU, held until the process ends,
+// shared by every call on that GPU (calls that overlap on one GPU race).
+namespace mdhp {
+namespace {
+
+constexpr int64_t kStaticEvents = MDHP_STATIC_MAX_EVENTS;
+constexpr int64_t kStaticWindows = MDHP_STATIC_MAX_WINDOWS;
+
+constexpr size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+// Byte offsets of the arrays in scratch, sized for the largest call.
+constexpr size_t kOffDt = 0;
+constexpr size_t kOffTau = kOffDt + up256(kStaticEvents * sizeof(float));
+constexpr size_t kOffD = kOffTau + up256(kStaticEvents * sizeof(float));
+constexpr size_t kOffBegin = kOffD + up256(kStaticEvents);
+constexpr size_t kOffN = kOffBegin + up256(kStaticWindows * sizeof(int64_t));
+constexpr size_t kOffT = kOffN + up256(kStaticWindows * sizeof(int32_t));
+constexpr size_t kOffEnd = kOffT + up256(kStaticWindows * sizeof(double));
+constexpr size_t kOffOrder = kOffEnd + up256(kStaticWindows * sizeof(float));
+constexpr size_t kOffCounts = kOffOrder + up256(kStaticWindows * sizeof(int32_t));
+constexpr size_t kOffWflags = kOffCounts + up256(kStaticWindows * MDHP_MAX_M * sizeof(int32_t));
+constexpr size_t kOffCounter = kOffWflags + up256(kStaticWindows * sizeof(int32_t));
+constexpr size_t kOffFlags = kOffCounter + 256;
+constexpr size_t kStaticBytes = kOffFlags + 256;
+static_assert(kStaticBytes == MDHP_STATIC_BYTES, "scratch layout and header disagree");
+
+__device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+// Per device: the address of that device's copy of scratch.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Window table of the call (natural order) and the cleared queue head.
+__global__ void static_windows_kernel(const int64_t* __restrict__ offsets, int64_t W,
+                                      int64_t n_events, int64_t* __restrict__ begin,
+                                      int32_t* __restrict__ n, int32_t* __restrict__ order,
+                                      int* counter) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < W; w += stride) {
+    int64_t b, e;
+    (void)window_bounds(offsets, w, W, n_events, b, e);
+    begin[w] = b;
+    n[w] = (int32_t)(e - b > INT32_MAX ? 0 : e - b);
+    order[w] = (int32_t)w;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    counter[0] = 0;
+    counter[1] = 0;
+  }
+}
+
+// Windows whose events failed validation: ll and the gradient are NaN.
+__global__ void static_flag_kernel(const int* __restrict__ wflags, int64_t W, int M,
+                                   double* ll, float* g_mu, float* g_alpha, float* g_beta) {
+  const int64_t MM = (int64_t)M * M;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < W * MM; i += stride) {
+    const int64_t w = i / MM, e = i % MM;
+    if (!wflags[w]) continue;
+    if (g_alpha) g_alpha[i] = __builtin_nanf("");
+    if (e < M && g_mu) g_mu[w * M + e] = __builtin_nanf("");
+    if (e == 0) {
+      ll[w] = __builtin_nan("");
+      if (g_beta) g_beta[w] = __builtin_nanf("");
+    }
+  }
+}
+
+}  // namespace
+}  // namespace mdhp
+
+extern "C" {
+
+mdhp_status mdhp_grad_static(const mdhp_batch* b, int32_t M, const float* mu, const float* alpha,
+                             const float* beta, double* ll, float* g_mu, float* g_alpha,
+                             float* g_beta, void* stream) {
+  if (!b) return fail(MDHP_E_INVAL, "grad_static: batch is NULL");
+  if (M < 1 || M > MDHP_MAX_M) return fail(MDHP_E_INVAL, "grad_static: M must be in [1, 64]");
+  if (b->W < 0 || b->n_events < 0) return fail(MDHP_E_INVAL, "grad_static: negative sizes");
+  if (b->W > kStaticWindows || b->n_events > kStaticEvents)
+    return fail(MDHP_E_INVAL, "grad_static: batch larger than the static workspace (at most " +
+                                  std::to_string(kStaticWindows) + " windows and " +
+                                  std::to_string(kStaticEvents) + " events)");
+  const bool grad = g_mu || g_alpha || g_beta;
+  if (grad && !(g_mu && g_alpha && g_beta))
+    return fail(MDHP_E_INVAL, "grad_static: give all three gradient arrays or none");
+  if (b->W == 0) return MDHP_OK;
+  if (!b->offsets || !b->T || (b->n_events > 0 && (!b->t || !b->dim)) || !mu || !alpha ||
+      !beta || !ll)
+    return fail(MDHP_E_INVAL, "grad_static: null pointer");
+  void* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) return hip_fail(e, "grad_static: scratch address");
+  unsigned char* sc = static_cast<unsigned char*>(base);
+  float* dt = reinterpret_cast<float*>(sc + kOffDt);
+  float* tau = reinterpret_cast<float*>(sc + kOffTau);
+  uint8_t* d8 = sc + kOffD;
+  int64_t* begin = reinterpret_cast<int64_t*>(sc + kOffBegin);
+  int32_t* n = reinterpret_cast<int32_t*>(sc + kOffN);
+  double* Tc = reinterpret_cast<double*>(sc + kOffT);
+  float* end_gap = reinterpret_cast<float*>(sc + kOffEnd);
+  int32_t* order = reinterpret_cast<int32_t*>(sc + kOffOrder);
+  int32_t* counts = reinterpret_cast<int32_t*>(sc + kOffCounts);
+  int* wflags = reinterpret_cast<int*>(sc + kOffWflags);
+  int* counter = reinterpret_cast<int*>(sc + kOffCounter);
+  int* flags = reinterpret_cast<int*>(sc + kOffFlags);
+
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t W = b->W;
+  const int grid = (int)std::min<int64_t>(W, 65536);
+  hipLaunchKernelGGL(static_windows_kernel, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, s,
+                     b->offsets, W, b->n_events, begin, n, order, counter);
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, flags);
+  hipLaunchKernelGGL(prepare_kernel, dim3(grid), dim3(256), 0, s, b->offsets, b->t, b->dim, b->T,
+                     nullptr, (int64_t)0, W, M, dt, tau, nullptr, d8, end_gap, Tc, counts, flags,
+                     b->n_events, wflags);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "grad_static: prepare");
+  const Events ev{W, dt, d8, begin, n, Tc, end_gap, order, counts, 0, tau, nullptr};
+  e = shared_eval_wide(ev, M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta, counter, s, grad);
+  if (e != hipSuccess) return hip_fail(e, "grad_static: launch");
+  const int64_t work = W * (int64_t)M * M;
+  hipLaunchKernelGGL(static_flag_kernel, dim3((unsigned)std::min<int64_t>((work + 255) / 256, 65536)),
+                     dim3(256), 0, s, wflags, W, M, ll, g_mu, g_alpha, g_beta);
+  e = hipGetLastError();
+  return e == hipSuccess ? MDHP_OK : hip_fail(e, "grad_static: launch");
 }
 
 }  // extern "C"

@@ -163,6 +163,11 @@ hipError_t shared_fit(const Events& ev, int M, int scatter, const FitParams& o, 
                       float* alpha, float* beta, double* ll, int* steps, int* status, int* evals,
                       float* ws, int64_t ws_floats, int* counter, hipStream_t s);
 bool shared_scatter_ok(int M, int scatter);
+// The lane-per-dimension kernels for any M <= 64 (groups of 32 lanes up to
+// M = 32, 64 above), default scatter; compact (not lane-major) events.
+hipError_t shared_eval_wide(const Events& ev, int M, const float* mu, const float* alpha,
+                            const float* beta, double* ll, float* g_mu, float* g_alpha,
+                            float* g_beta, int* counter, hipStream_t s, bool grad);
 // Floats of workspace the L-BFGS fit needs for a plan of W windows.
 int64_t shared_lbfgs_workspace(int M, int64_t W);
 hipError_t pair_eval(const Events& ev, int M, const float* mu, const float* alpha,

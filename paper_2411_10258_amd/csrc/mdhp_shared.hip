@@ -1144,6 +1144,16 @@ hipError_t shared_eval(const Events& ev, int M, int scatter, const float* mu, co
   });
 }
 
+hipError_t shared_eval_wide(const Events& ev, int M, const float* mu, const float* alpha,
+                            const float* beta, double* ll, float* g_mu, float* g_alpha,
+                            float* g_beta, int* counter, hipStream_t s, bool grad) {
+  if (M <= 32)
+    return launch_shared_eval<32, kScatter>(ev, M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta,
+                                            counter, s, grad);
+  return launch_shared_eval<64, kScatter>(ev, M, mu, alpha, beta, ll, g_mu, g_alpha, g_beta,
+                                          counter, s, grad);
+}
+
 hipError_t shared_fit(const Events& ev, int M, int scatter, const FitParams& o, float* mu,
                       float* alpha, float* beta, double* ll, int* steps, int* status, int* evals,
                       float* ws, int64_t ws_floats, int* counter, hipStream_t s) {

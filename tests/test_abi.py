@@ -58,6 +58,24 @@ def test_host_error_paths():
                               None, None) == -1
     assert lib.mdhp_plan_windows(None) == 0
     lib.mdhp_plan_destroy(None)
+    # allocation-free entry point: sizes beyond its workspace, partial
+    # gradient outputs and empty batches are settled on the host
+    dummy = ctypes.c_void_p(16)
+    big = _lib.MdhpBatch(65537, 10, dummy, dummy, dummy, dummy)
+    assert lib.mdhp_grad_static(ctypes.byref(big), 4, dummy, dummy, dummy, dummy, None, None,
+                                None, None) == -1
+    assert lib.mdhp_last_error(buf, 256) == -1 and b"static workspace" in buf.value
+    big = _lib.MdhpBatch(1, 4194305, dummy, dummy, dummy, dummy)
+    assert lib.mdhp_grad_static(ctypes.byref(big), 4, dummy, dummy, dummy, dummy, None, None,
+                                None, None) == -1
+    one = _lib.MdhpBatch(1, 10, dummy, dummy, dummy, dummy)
+    assert lib.mdhp_grad_static(ctypes.byref(one), 4, dummy, dummy, dummy, dummy, dummy, None,
+                                None, None) == -1
+    assert lib.mdhp_grad_static(ctypes.byref(one), 65, dummy, dummy, dummy, dummy, None, None,
+                                None, None) == -1
+    empty = _lib.MdhpBatch(0, 0, None, None, None, None)
+    assert lib.mdhp_grad_static(ctypes.byref(empty), 4, None, None, None, None, None, None,
+                                None, None) == 0
 
 
 def test_binding_refuses_missing_library(monkeypatch, tmp_path):
