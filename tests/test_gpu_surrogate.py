@@ -140,7 +140,8 @@ def test_warm_start_falls_back_to_cold(gpu, oracle_lib, synth_lib):
 
 def test_checkpoint_round_trip(gpu, tmp_path):
     """save/load restores weights, both Adam moments and the step: the next
-    training step of the restored network is bitwise the original's."""
+    training step of the restored network gives bitwise the original's
+    weights."""
     import torch
     from paper_2411_10258_amd import _lib, surrogate
     rng = np.random.default_rng(4)
@@ -162,7 +163,10 @@ def test_checkpoint_round_trip(gpu, tmp_path):
     la = a.train_step(x, t, 1e-3).item()
     lb = b.train_step(x, t, 1e-3).item()
     torch.cuda.synchronize()
-    assert la == lb
+    # the step's weights are bitwise equal; the reported loss is an FP64
+    # atomic sum over the batch, equal up to its summation order
+    assert torch.equal(a.get_weights(), b.get_weights())
+    assert abs(la - lb) <= 1e-12 * abs(la)
     assert torch.equal(a.get_weights(), b.get_weights())
     # Another shape, a foreign file, a truncated file, a missing file.
     c = surrogate.Surrogate(16, hidden=256, max_batch=8, seed=1)
