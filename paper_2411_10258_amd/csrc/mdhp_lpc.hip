@@ -1029,7 +1029,7 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
       }
       const double gamma0 = 0.01 / gmax;
       for (int i = 0; i < h; ++i) {
-        const int j = (head - 1 - i + kMaxHistory) % kMaxHistory;
+        const int j = (head - 1 - i + m_hist) % m_hist;
         float sj[K], yj[K];  // both loads in flight together
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -1049,7 +1049,7 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
       for (int k = 0; k < K; ++k) qv[k] *= gamma;
       team_sync<NW>();
       for (int i = h - 1; i >= 0; --i) {
-        const int j = (head - 1 - i + kMaxHistory) % kMaxHistory;
+        const int j = (head - 1 - i + m_hist) % m_hist;
         float sj[K], yj[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -1140,7 +1140,7 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
         if (t == 0) sh.rho[head] = 1.0 / sy;
         sy_new = sy;
         yy_new = yy;
-        head = (head + 1) % kMaxHistory;
+        head = (head + 1) % m_hist;
         h += 1;
         team_sync<NW>();
       }

@@ -226,10 +226,19 @@ __device__ __noinline__ void slow_decay_sums(SharedLds<P>& sh, const float* __re
 }
 
 // Evaluates one window with the parameters already in LDS (alpha, mu,
-// colsum, beta).  Results: sh.scal[0] = ll, and if GRAD: gR64[k] holds
+// colsum, beta).  ASM_GR (P = 64, the evaluation kernel): 1 / lambda read
+// from its lane as a scalar, the G_R row update as the fixed-register
+// indexed FMA of gr_row_fma, and tie-free blocks without the pending-count
+// select.  Without it (the fit kernels): 1 / lambda through LDS and the
+// compiler's indexed access to the register rows.  Built into the fit
+// kernels at their register budget (two workgroups per CU), the former gave
+// wrong likelihoods from the second window a workgroup ran on (see
+// tests/test_gpu_multiwindow.py), with no cause found in the generated code,
+// so it stays in the evaluation kernel only, where every window is checked.
+// Results: sh.scal[0] = ll, and if GRAD: gR64[k] holds
 // G_R[e] for e = tid + k * kBlock (FP64), sh.Cn, sh.Fn, sh.gmu (= d ll/d mu),
 // sh.scal[1] = d ll / d beta.  cnt_w: the window's events per dimension.
-template <int P, bool GRAD, int SB>
+template <int P, bool GRAD, int SB, bool ASM_GR = false>
 __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __restrict__ dtg,
                             const uint8_t* __restrict__ dg, const float* __restrict__ taug,
                             int64_t begin, int n, double T,
@@ -394,14 +403,14 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
             Rin = x + ao.y;  // the event itself is pending until time moves on
           });
         };
-        if (tie_free) recur(std::true_type{});
+        if (ASM_GR && tie_free) recur(std::true_type{});
         else recur(std::false_type{});
         float lam = group_reduce_scatter<P, B>(L);
         const float4 me = meta[sb + ev_l];
         const bool valid = me.w >= 0.f;
         lam += me.w;
         llp += (lead && valid) ? __logf(lam) : 0.f;
-        if constexpr (kRegGR) {
+        if constexpr (kRegGR && ASM_GR) {
           // 1 / lambda of event j is in lane j << SH; read as a scalar, it
           // scales R(j) into row d_j of the wave's G_R registers (one
           // indexed FMA) and S into the decay gradient.
@@ -433,7 +442,17 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
           }
 #pragma unroll
           for (int j = 0; j < B; ++j) {
-            atomicAdd(&gRc[Dj[j] * P + lane], wv[j] * Rj[j]);
+            const float x = wv[j] * Rj[j];
+            if constexpr (kRegGR) {
+              // Row d of the wave's G_R registers (d is uniform: one event).
+              const int d = __builtin_amdgcn_readfirstlane(Dj[j]);
+              const int dl = d & 31;
+              const bool hi = d >= 32;
+              gacc0[dl] += hi ? 0.f : x;
+              gacc1[dl] += hi ? x : 0.f;
+            } else {
+              atomicAdd(&gRc[Dj[j] * P + lane], x);
+            }
             gbp = fmaf(wv[j], AS[j], gbp);
           }
           wave_sync();  // wb is rewritten by the next events
@@ -659,7 +678,8 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_eva
     const int64_t w = ev.order[q];
     load_params(sh, mu, alpha, beta, w, M);
     const double T = ev.T[w];
-    eval_window<P, GRAD, SB>(sh, ev.dt, ev.d, ev.tau, ev.begin[w], ev.n[w], T, ev.end_gap[w], M, ev.counts + w * M, gR64);
+    eval_window<P, GRAD, SB, true>(sh, ev.dt, ev.d, ev.tau, ev.begin[w], ev.n[w], T,
+                                   ev.end_gap[w], M, ev.counts + w * M, gR64);
     if (tid == 0) ll[w] = sh.scal[0];
     if constexpr (GRAD) {
       if (tid == 0) g_beta[w] = (float)sh.scal[1];
@@ -943,7 +963,7 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_lbf
         }
         const double gamma0 = 0.01 / gmax;
         for (int i = 0; i < h; ++i) {
-          const int j = (head - 1 - i + kMaxHistory) % kMaxHistory;
+          const int j = (head - 1 - i + m_hist) % m_hist;
           double v[1] = {0.0};
 #pragma unroll
           for (int k = 0; k < K; ++k) v[0] += (double)Sv(j, k) * qv[k];
@@ -957,7 +977,7 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_lbf
 #pragma unroll
         for (int k = 0; k < K; ++k) qv[k] *= gamma;
         for (int i = h - 1; i >= 0; --i) {
-          const int j = (head - 1 - i + kMaxHistory) % kMaxHistory;
+          const int j = (head - 1 - i + m_hist) % m_hist;
           double v[1] = {0.0};
 #pragma unroll
           for (int k = 0; k < K; ++k) v[0] += (double)Yv(j, k) * qv[k];
@@ -1040,7 +1060,7 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_lbf
           if (tid == 0) rho_s[head] = 1.0 / sums[0];
           sy_new = sums[0];
           yy_new = sums[2];
-          head = (head + 1) % kMaxHistory;
+          head = (head + 1) % m_hist;
           h += 1;
           __syncthreads();
         }
