@@ -2,31 +2,37 @@
 likelihood tolerance 1e-5, warm start vs cold start, L-BFGS vs gradient
 descent; likelihood+gradient event evaluations per second.
 
-Workload (default): 4,096 synthetic windows, M = 16 dimensions, one decay
-per window in {0.5, 1, 2}, log-normal event counts (median 1,000, clipped to
-[100, 20,000]), simulated by Ogata thinning with seed 2024.
+Workload (default, the headline): 16,384 synthetic windows, M = 64
+dimensions, one decay per window in {0.5, 1, 2}, log-normal event counts
+(median 5,000, sigma 1.2, clipped to [500, 50,000]; ~151M events),
+simulated by Ogata thinning with seed 2024.  The 4,096-window M = 16 batch
+(median 1,000, clipped to [100, 20,000]) runs after it and is reported
+under "batch_m16" (--no-m16 skips it; --workload batch_m16 makes it the
+headline).
 
 Rules (both timed, from both starts): projected L-BFGS (memory 5, chosen on
-other batches of the same distribution; <= 500 updates) and gradient descent as projected Adam (lr 3e-2, <= 500 updates),
-both stopping when an update changes ll by at most 1e-7 relative.  A fit
-counts when its final ll is within 1e-5 max(|ll*|, N) of the window's
-optimum ll* (N events; at the optimum the compensator equals N, so N is the
-likelihood's own scale, the one on which FP32 and FP64 agree to 1e-5): the
-best of a long untimed L-BFGS run (memory 16, 3,000 updates, no likelihood
-stop) and every timed run, itself checked against the FP64 oracle's
-long-run optimum on a sample.
+other batches of the M = 16 distribution; <= 500 updates) and gradient
+descent as projected Adam (lr 3e-2, <= 500 updates), both stopping when an
+update changes ll by at most 1e-7 max(|ll|, N).  A fit counts when its final
+ll is within 1e-5 max(|ll*|, N) of the window's optimum ll* (N events; at
+the optimum the compensator equals N, so N is the likelihood's own scale,
+the one on which FP32 and FP64 agree to 1e-5); the count within 1e-5 |ll*|
+is reported beside it.  ll* is the best of a long untimed L-BFGS run (memory
+16, 1,500 updates for M = 64, 3,000 for M = 16, no likelihood stop) and
+every timed run, itself checked against the FP64 oracle's long-run optimum
+on a sample.
 
 Before timing (reported separately, not in the timed steps): the warm-start
 network is trained on windows simulated with seed 1024 and fitted from the
-cold start by the same GPU solver.
+cold start by the same GPU solver, and the plan's schedule is autotuned.
 
 One timed step = the whole hot path over the batch, inputs resident in HBM:
   cold:  mdhp_plan_create (validation, FP64 gaps, per-dimension counts,
-         largest-first order, lane-major layout) + mdhp_cold_start +
-         mdhp_fit_batch (one persistent launch: per iteration the
-         likelihood and gradient of every window, the update, the stop rule);
+         largest-first order) + mdhp_cold_start + mdhp_fit_batch (one
+         persistent launch: per iteration the likelihood and gradient of
+         every window, the update, the stop rule);
   warm:  mdhp_plan_create + mdhp_cold_start + mdhp_features + network forward
-         (BF16 MFMA) + mdhp_warm_start (two likelihood passes, per-window
+         (BF16 MFMA) + mdhp_warm_start (likelihood passes, per-window
          fallback to the cold start) + mdhp_fit_batch.
 
 ``value`` is warm-start L-BFGS fits at tolerance per second (cold start with
@@ -97,6 +103,8 @@ def cpu_baseline(b, opts_kw, sample_windows: int, gpu_params, lstar_gpu, scale):
     idx = np.arange(min(sample_windows, b.W))
     s = b.subset(idx)
     mu, alpha, beta = host_cold_start(s)
+    # The oracle's thread pool: every logical CPU, at most 16 (the host
+    # share of one GPU on the machines this runs on).
     threads = min(16, os.cpu_count() or 1)
     o = oracle.FitOpts(**opts_kw)
     t0 = time.perf_counter()
@@ -105,11 +113,13 @@ def cpu_baseline(b, opts_kw, sample_windows: int, gpu_params, lstar_gpu, scale):
     evals = float(np.sum(s.counts * r[6]))
     ref = oracle.fit(s.offsets, s.t, s.dim, s.T, s.M, mu, alpha, beta,
                      oracle.FitOpts(**{**opts_kw, "optimizer": 2, "ll_tol": 1e-13,
-                                       "max_steps": 5000, "history": 16}), nthreads=threads)
+                                       "max_steps": 5000 if s.M <= 16 else 1500,
+                                       "history": 16}), nthreads=threads)
     lstar = np.maximum(ref[3], r[3])
     sc = scale[idx]
     conv = int(np.sum((lstar - r[3]) <= 1e-5 * np.maximum(np.abs(lstar), s.counts)))
     out = {"value": conv / dt, "unit": "fits/s", "cores": threads, "kind": "oracle",
+           "host": host_info(),
            "sample": f"first {s.W} windows ({s.n_events} events) of the same workload, cold "
                      f"start, same rule and options; {dt:.1f} s",
            "event_evals_per_s": evals / dt, "windows_per_s": s.W / dt}
@@ -135,7 +145,7 @@ def bench_pair(args, dev) -> int:
     import synth
     import paper_2411_10258_amd as mdhp
 
-    b = synth.pair_m32(W=1024 if args.windows == 4096 else args.windows, seed=2024)
+    b = synth.pair_m32(W=args.windows, seed=2024)
     g = np.random.default_rng(11)
     mu = torch.from_numpy((b.mu * g.uniform(0.5, 1.5, b.mu.shape)).astype(np.float32)).to(dev)
     al = torch.from_numpy((b.alpha * g.uniform(0.5, 1.5, b.alpha.shape)).astype(np.float32)).to(dev)
@@ -197,117 +207,80 @@ def bench_pair(args, dev) -> int:
     return 0
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["batch_m16", "large_m64", "pair_m32"],
-                    default="batch_m16",
-                    help="batch_m16: warm vs cold fits of 4,096 M=16 windows (default); "
-                         "large_m64: cold fits of 16,384 M=64 windows (~151M events); "
-                         "pair_m32: likelihood+gradient passes over 1,024 x 5,000 events "
-                         "with per-pair decays")
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--windows", type=int, default=4096)
-    ap.add_argument("--max-steps", type=int, default=500, help="L-BFGS update limit")
-    ap.add_argument("--gds-steps", type=int, default=500, help="projected Adam update limit")
-    ap.add_argument("--ref-steps", type=int, default=3000,
-                    help="updates of the reference-optimum L-BFGS run")
-    ap.add_argument("--ll-tol", type=float, default=1e-7)
-    ap.add_argument("--history", type=int, default=5,
-                    help="L-BFGS memory (5: chosen on batches other than the timed one)")
-    ap.add_argument("--optimizer", choices=["lbfgs", "gds"], default="lbfgs",
-                    help="rule of the headline value (both rules are always timed)")
-    ap.add_argument("--lr", type=float, default=3e-2, help="step size of projected Adam")
-    ap.add_argument("--no-gds", action="store_true", help="skip the projected Adam runs")
-    ap.add_argument("--train-windows", type=int, default=65536)
-    ap.add_argument("--epochs", type=int, default=20)
-    ap.add_argument("--no-warm", action="store_true", help="time cold-start fits only")
-    ap.add_argument("--cpu-sample", type=int, default=96)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default schedule instead of tuning it on the batch first")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
-                    help="only run a plain device-to-device copy of BYTES bytes (5 times), "
-                         "the reference for scaling HBM traffic counters")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: windows are independent, so more GPUs would "
-              "each fit their own share; pass --gpus 1", file=sys.stderr)
-        return 2
+def host_info() -> dict:
+    """Host CPU of the run: logical CPUs and the model name."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
 
+
+WORKLOADS = {
+    "large_m64": "16,384 windows, M=64, shared decay, log-normal counts median 5,000 "
+                 "clipped [500, 50,000]",
+    "batch_m16": "4,096 windows, M=16, shared decay, log-normal counts median 1,000 "
+                 "clipped [100, 20,000]",
+}
+
+
+def run_fit_workload(args, name: str, dev, log, cpu: bool) -> dict:
+    """Warm vs cold fits of one batch workload under projected L-BFGS and
+    projected Adam; returns the result record (the bench line's body)."""
     import numpy as np
     import torch
 
     import synth
     import paper_2411_10258_amd as mdhp
-    from paper_2411_10258_amd import warmstart
+    from paper_2411_10258_amd import graph, warmstart
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a HIP device", file=sys.stderr)
-        return 1
-    dev = torch.device("cuda:0")
-    if args.copy_calibration:
-        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": src.numel() * 4}))
-        return 0
-
-    if args.workload == "pair_m32":
-        return bench_pair(args, dev)
-    if args.workload == "large_m64":
-        args.no_gds = True  # 500 projected Adam updates of 151M events: minutes per run
-        if args.train_windows == 65536:
-            args.train_windows = 4096
-        if args.windows == 4096:
-            args.windows = 16384
-        if args.cpu_sample == 96:
-            args.cpu_sample = 16
+    large = name == "large_m64"
+    W = args.windows or (16384 if large else 4096)
+    train_windows = args.train_windows or (4096 if large else 65536)
+    ref_steps = args.ref_steps or (1500 if large else 3000)
+    cpu_sample = args.cpu_sample or (16 if large else 96)
     lb_kw = dict(max_steps=args.max_steps, optimizer=mdhp.OPT_LBFGS, ll_tol=args.ll_tol,
                  history=args.history)
     gd_kw = dict(max_steps=args.gds_steps, optimizer=mdhp.OPT_PADAM, ll_tol=args.ll_tol,
                  lr=args.lr)
     main_kw = lb_kw if args.optimizer == "lbfgs" else gd_kw
-    log = lambda m: print(m, file=sys.stderr, flush=True)
 
-    if args.workload == "large_m64":
-        t_gen = time.perf_counter()
-        b = synth.large_m64(W=args.windows, seed=2024)
-        log(f"generated {b.W} windows, {b.n_events} events in {time.perf_counter() - t_gen:.1f}s")
-    else:
-        b = synth.batch_m16(W=args.windows, seed=2024)
+    t_gen = time.perf_counter()
+    b = synth.large_m64(W=W, seed=2024) if large else synth.batch_m16(W=W, seed=2024)
+    gen_s = time.perf_counter() - t_gen
+    log(f"[{name}] generated {b.W} windows, {b.n_events} events in {gen_s:.1f}s")
     db = warmstart.DeviceBatch.of(b, dev)
 
-    train_info = None
-    net = None
+    train_info, net = None, None
     if not args.no_warm:
         t0 = time.perf_counter()
-        ts = warmstart.build_training_set(b.M, args.train_windows, seed=1024,
+        ts = warmstart.build_training_set(b.M, train_windows, seed=1024,
                                           opts=mdhp.FitOptions(**{**lb_kw, "max_steps": 1000}),
                                           log=log)
         net, losses, train_s = warmstart.train_surrogate(ts, b.M, epochs=args.epochs, log=log)
-        train_info = {"windows": int(ts.ok.sum()), "simulate_s": ts.gen_s, "cold_fit_s": ts.fit_s,
-                      "train_s": train_s, "epochs": args.epochs,
+        train_info = {"windows": int(ts.ok.sum()), "simulate_s": ts.gen_s,
+                      "cold_fit_s": ts.fit_s, "train_s": train_s, "epochs": args.epochs,
                       "loss_first_last": [losses[0], losses[-1]],
                       "total_s": time.perf_counter() - t0}
 
-    # Schedule autotuning (untimed, like the network's training): the plan's
-    # candidate schedules timed on this batch with the main fit rule.
+    # Schedule autotuning (untimed, like the network's training).
     plan = mdhp.Plan(db.offsets, db.t, db.dim, db.T, b.M, mdhp.BETA_SHARED, device=dev)
     default_schedule = plan.schedule
     tuned, tune_info = default_schedule, None
     if not args.no_autotune:
         t0 = time.perf_counter()
-        reps = 1 if args.workload == "large_m64" else 3  # seconds per large fit
+        reps = 1 if large else 3  # seconds per large fit
         r = plan.autotune(db.offsets, db.t, db.dim, db.T, mdhp.FitOptions(**main_kw), reps=reps)
         tune_info = dict(r, seconds=time.perf_counter() - t0, default=default_schedule,
                          objective=f"fastest of {reps} timed fits of the batch from the cold "
                                    "start with the main rule per candidate, after one untimed fit")
         tuned = r["chosen"]
     plan.close()
+    log(f"[{name}] schedule {tuned}")
 
     def step(warm, opts_kw, events=None):
         """One pass of the whole path: plan, initial point, fit."""
@@ -331,7 +304,7 @@ def main() -> int:
             events[2].record()
         return plan, (mu, al, be), ll, st, stat, ev, used
 
-    def timed(warm, opts_kw):
+    def timed(label, warm, opts_kw):
         for _ in range(args.warmup):
             plan, *_ = step(warm, opts_kw)
             torch.cuda.synchronize()
@@ -352,22 +325,22 @@ def main() -> int:
                    used=None if used is None else used.cpu().numpy())
         for (p, *_), _ in res:
             p.close()
+        log(f"[{name}] {label}: {out['ms']:.1f} ms per step, fit kernel {k_ms:.1f} ms")
         return out
 
-    runs = {"cold_lbfgs": timed(False, lb_kw)}
+    runs = {"cold_lbfgs": timed("cold_lbfgs", False, lb_kw)}
     if not args.no_gds:
-        runs["cold_gds"] = timed(False, gd_kw)
+        runs["cold_gds"] = timed("cold_gds", False, gd_kw)
     if net is not None:
-        runs["warm_lbfgs"] = timed(True, lb_kw)
+        runs["warm_lbfgs"] = timed("warm_lbfgs", True, lb_kw)
         if not args.no_gds:
-            runs["warm_gds"] = timed(True, gd_kw)
-    main_label = ("warm_" if net is not None else "cold_") + (
-        "lbfgs" if args.optimizer == "lbfgs" else "gds")
+            runs["warm_gds"] = timed("warm_gds", True, gd_kw)
+    rule = "lbfgs" if args.optimizer == "lbfgs" else "gds"
+    main_label = ("warm_" if net is not None else "cold_") + rule
     main_run = runs[main_label]
 
     # The main pipeline (initial point + fit, on a prepared plan) eagerly and
     # as one captured HIP graph.
-    from paper_2411_10258_amd import graph
     plan = mdhp.Plan(db.offsets, db.t, db.dim, db.T, b.M, mdhp.BETA_SHARED, device=dev,
                      schedule=tuned)
     gopts = mdhp.FitOptions(**main_kw)
@@ -397,32 +370,35 @@ def main() -> int:
     # Reference optimum (untimed): a long L-BFGS run from the cold start
     # (memory 16, no likelihood stop); a window's optimum is the best
     # likelihood any run reached.
-    plan = mdhp.Plan(db.offsets, db.t, db.dim, db.T, b.M, mdhp.BETA_SHARED, device=dev)
+    plan = mdhp.Plan(db.offsets, db.t, db.dim, db.T, b.M, mdhp.BETA_SHARED, device=dev,
+                     schedule=tuned)
     mu0, al0, be0 = plan.cold_start()
-    ref = plan.fit(mu0, al0, be0, mdhp.FitOptions(max_steps=args.ref_steps,
-                                                  optimizer=mdhp.OPT_LBFGS, ll_tol=0.0,
-                                                  history=16))
+    ref = plan.fit(mu0, al0, be0, mdhp.FitOptions(max_steps=ref_steps, optimizer=mdhp.OPT_LBFGS,
+                                                  ll_tol=0.0, history=16))
     lstar_ref = ref[3].cpu().numpy()
     plan.close()
     lstar = lstar_ref.copy()
     for r in runs.values():
         lstar = np.maximum(lstar, np.where(np.isfinite(r["ll"]), r["ll"], -np.inf))
+    log(f"[{name}] reference optimum done")
 
-    # Scale of a window's likelihood: max(|ll*|, N).  lambda is linear in
-    # (mu, alpha), so at the optimum the compensator equals N; N is therefore
-    # a lower bound of the sum of magnitudes of the likelihood's terms, the
-    # scale on which FP32 evaluations and the FP64 oracle agree to 1e-5.
-    scale = np.maximum(np.abs(lstar_ref), b.counts.astype(np.float64))
+    # A fit counts when its final ll is within 1e-5 of the window's optimum
+    # on the likelihood's scale max(|ll*|, N) (lambda is linear in (mu,
+    # alpha), so at the optimum the compensator equals N); the count relative
+    # to |ll*| alone is reported beside it.
+    counts = b.counts.astype(np.float64)
+    scale = np.maximum(np.abs(lstar_ref), counts)
 
     def fits(r):
-        """Windows whose final likelihood is within 1e-5 of the optimum (on that scale)."""
-        return int(np.sum((lstar - r["ll"]) <= 1e-5 * np.maximum(np.abs(lstar), b.counts)))
+        return int(np.sum((lstar - r["ll"]) <= 1e-5 * np.maximum(np.abs(lstar), counts)))
+
+    def fits_abs(r):
+        return int(np.sum((lstar - r["ll"]) <= 1e-5 * np.abs(lstar)))
 
     def rate(r):
         return fits(r) / (r["ms"] * 1e-3)
 
-    evals = float(np.sum(b.counts.astype(np.float64) * main_run["evals"]))
-    ms = main_run["ms"]
+    evals = float(np.sum(counts * main_run["evals"]))
     k_ms = main_run["kernel_ms"]
     achieved = evals * flops_per_event_eval(b.M) / (k_ms * 1e-3) / 1e12
     lbfgs_main = main_kw is lb_kw
@@ -432,39 +408,28 @@ def main() -> int:
     else:          # workgroup-per-window kernels
         kname = "shared_lbfgs_kernel_P64" if lbfgs_main else "shared_fit_kernel_P64"
         ksrc = "mdhp_shared.hip"
-    workload = (f"batch_m16: {b.W} windows, M=16, shared decay, log-normal counts median 1000 "
-                f"clipped [100, 20000], {b.n_events} events" if b.M == 16 else
-                f"large_m64: {b.W} windows, M=64, shared decay, log-normal counts median 5000 "
-                f"clipped [500, 50000], {b.n_events} events")
     out = {
-        "metric": METRIC,
         "value": rate(main_run),
-        "unit": "fits/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32 (f64 per-window sums)",
-        "data": "synthetic (Ogata thinning, seed 2024" + ("; network trained on seed 1024)"
-                                                           if net is not None else ")"),
-        "config": {"workload": workload + f"; {main_label.replace('_', ' start, ')}; a fit "
-                               f"counts when its ll is within 1e-5 of the window's optimum",
-                   "global_batch": b.W, "events": b.n_events, "parallelism": "none (1 GPU)"},
-        "runs": {k: {"fits_per_s": rate(r), "ms_per_step": r["ms"], "fit_kernel_ms": r["kernel_ms"],
-                     "fits_within_1e-5": fits(r), "mean_updates": float(np.mean(r["steps"])),
+        "ms_per_step": main_run["ms"],
+        "workload": f"{name}: {WORKLOADS[name]}, {b.n_events} events; "
+                    f"{main_label.replace('_', ' start, ')}; a fit counts when its ll is within "
+                    f"1e-5 max(|ll*|, N) of the window's optimum ll*",
+        "global_batch": b.W, "events": b.n_events,
+        "runs": {k: {"fits_per_s": rate(r), "ms_per_step": r["ms"],
+                     "fit_kernel_ms": r["kernel_ms"],
+                     "fits_within_1e-5": fits(r),
+                     "fits_within_1e-5_of_abs_ll": fits_abs(r),
+                     "mean_updates": float(np.mean(r["steps"])),
                      "mean_evals": float(np.mean(r["evals"])),
                      "stopped_frac": float(np.mean((r["status"] == mdhp.FIT_CONVERGED) |
                                                    (r["status"] == mdhp.FIT_STALLED))),
                      **({"warm_used_frac": float(np.mean(r["used"]))} if r["used"] is not None
                         else {})}
                  for k, r in runs.items()},
-        "rules": {"lbfgs": f"projected L-BFGS, memory {args.history}, <= {args.max_steps} updates, stop at "
-                           f"|dll| <= {args.ll_tol} max(|ll|, N)",
+        "rules": {"lbfgs": f"projected L-BFGS, memory {args.history}, <= {args.max_steps} "
+                           f"updates, stop at |dll| <= {args.ll_tol} max(|ll|, N)",
                   "gds": f"projected Adam (lr {args.lr}), <= {args.gds_steps} updates, same stop"},
-        "event_evals_per_s": evals / (ms * 1e-3),
+        "event_evals_per_s": evals / (main_run["ms"] * 1e-3),
         "fit_kernel_ms": k_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
@@ -473,19 +438,122 @@ def main() -> int:
                      "kernel": kname, "flops_per_event_eval": flops_per_event_eval(b.M),
                      "event_evals_per_launch": evals},
         "reference_optimum": f"GPU projected L-BFGS from the cold start, memory 16, "
-                             f"{args.ref_steps} updates without likelihood stop",
+                             f"{ref_steps} updates without likelihood stop, with every timed run",
+        "input_generation_s": gen_s,
     }
-    if "cold_gds" in runs and main_label.startswith("warm"):
-        out["warm_speedup_vs_cold_gds"] = rate(main_run) / max(rate(runs["cold_gds"]), 1e-30)
     if net is not None:
-        out["warm_speedup_same_rule"] = rate(main_run) / max(
-            rate(runs["cold_" + main_label.split("_")[1]]), 1e-30)
+        same = "cold_" + rule
+        out["warm_speedup_same_rule"] = rate(main_run) / max(rate(runs[same]), 1e-30)
+        out["warm_start_chosen_frac"] = float(np.mean(main_run["used"]))
+        if "cold_gds" in runs and rule == "lbfgs":
+            # the update rule's gain, not the network's: reported apart
+            # (null when no cold projected-Adam fit reached the tolerance)
+            cg = rate(runs["cold_gds"])
+            out["warm_lbfgs_over_cold_gds"] = rate(main_run) / cg if cg > 0 else None
         out["surrogate_training"] = train_info
     out["schedule"] = tune_info if tune_info is not None else {"default": default_schedule}
     out["graph"] = graph_info
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(b, main_kw, args.cpu_sample, main_run["params"],
+    if cpu:
+        out["cpu_baseline"] = cpu_baseline(b, main_kw, cpu_sample, main_run["params"],
                                            lstar_ref, scale)
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["large_m64", "batch_m16", "pair_m32"],
+                    default="large_m64",
+                    help="large_m64: warm vs cold fits of 16,384 M=64 windows (~151M events, "
+                         "default; the M=16 batch follows as extra keys unless --no-m16); "
+                         "batch_m16: warm vs cold fits of 4,096 M=16 windows; "
+                         "pair_m32: likelihood+gradient passes over 1,024 x 5,000 events "
+                         "with per-pair decays")
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--windows", type=int, default=0, help="0: the workload's size")
+    ap.add_argument("--max-steps", type=int, default=500, help="L-BFGS update limit")
+    ap.add_argument("--gds-steps", type=int, default=500, help="projected Adam update limit")
+    ap.add_argument("--ref-steps", type=int, default=0,
+                    help="updates of the reference-optimum L-BFGS run (0: 1,500 for M=64, "
+                         "3,000 for M=16)")
+    ap.add_argument("--ll-tol", type=float, default=1e-7)
+    ap.add_argument("--history", type=int, default=5,
+                    help="L-BFGS memory (5: chosen on batches other than the timed one)")
+    ap.add_argument("--optimizer", choices=["lbfgs", "gds"], default="lbfgs",
+                    help="rule of the headline value (both rules are always timed)")
+    ap.add_argument("--lr", type=float, default=3e-2, help="step size of projected Adam")
+    ap.add_argument("--no-gds", action="store_true", help="skip the projected Adam runs")
+    ap.add_argument("--train-windows", type=int, default=0,
+                    help="0: 4,096 for M=64, 65,536 for M=16")
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--no-warm", action="store_true", help="time cold-start fits only")
+    ap.add_argument("--no-m16", action="store_true",
+                    help="large_m64 only: skip the M=16 batch's extra keys")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="0: 16 for M=64, 96 for M=16")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default schedule instead of tuning it on the batch first")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes (5 times), "
+                         "the reference for scaling HBM traffic counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: windows are independent, so more GPUs would "
+              "each fit their own share; pass --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4}))
+        return 0
+
+    if args.workload == "pair_m32":
+        if not args.windows:
+            args.windows = 1024
+        return bench_pair(args, dev)
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    r = run_fit_workload(args, args.workload, dev, log, cpu=not args.no_cpu)
+    out = {
+        "metric": METRIC,
+        "value": r.pop("value"),
+        "unit": "fits/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r.pop("ms_per_step"),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 per-window sums)",
+        "data": "synthetic (Ogata thinning, seed 2024" + ("; network trained on seed 1024)"
+                                                           if not args.no_warm else ")"),
+        "config": {"workload": r.pop("workload"), "global_batch": r.pop("global_batch"),
+                   "events": r.pop("events"), "parallelism": "none (1 GPU)"},
+    }
+    out.update(r)
+    out["host"] = host_info()
+    if args.workload == "large_m64" and not args.no_m16:
+        m16_args = argparse.Namespace(**{**vars(args), "windows": 0, "train_windows": 0,
+                                         "ref_steps": 0, "cpu_sample": 0, "steps": 5,
+                                         "warmup": 1})
+        m16 = run_fit_workload(m16_args, "batch_m16", dev, log, cpu=not args.no_cpu)
+        out["batch_m16"] = {k: m16[k] for k in
+                            ("value", "ms_per_step", "workload", "runs", "event_evals_per_s",
+                             "fit_kernel_ms", "roofline", "warm_speedup_same_rule",
+                             "warm_start_chosen_frac", "warm_lbfgs_over_cold_gds", "schedule",
+                             "cpu_baseline") if k in m16}
+        out["batch_m16"]["steps"], out["batch_m16"]["warmup"] = 5, 1
     print(json.dumps(out), flush=True)
     return 0
 
