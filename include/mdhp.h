@@ -373,10 +373,13 @@ mdhp_status mdhp_surrogate_load(mdhp_surrogate* s, const char* path, float* extr
                                 int64_t extra_cap, int64_t* n_extra, void* stream);
 
 /* Warm start for a plan with one decay per window.  pred[W][M + M*M + 1]
- * (device f32) is the network output for the plan's windows, in z-scored
- * log-parameters: y = pred * stdv + mean gives (log mu, log alpha, log beta)
- * in the parameter layout order.  Writes mu/alpha/beta = exp(y) (mu and
- * beta clamped to opts' floors), evaluates ll at them and at the cold start
+ * (device f32) is the network output for the plan's windows, z-scored:
+ * y = pred * stdv + mean gives, in the parameter layout order,
+ * log(mu_m T / max(N_m, 0.5)) (the log of mu_m over the window's rate of
+ * dimension m), the branching entries alpha_mn / beta, and log beta.
+ * Writes beta = exp(y_beta), mu_m = exp(y_m) max(N_m, 0.5) / T (both
+ * clamped to opts' floors) and alpha_mn = max(y_mn, 0) beta, evaluates ll
+ * at them and at the cold start
  * (mu_cold, alpha_cold, beta_cold), keeps the cold start for windows where
  * it is at least as likely or the warm one is not finite, and records the
  * choice in used_warm[W] (1 = warm).  Enqueued on stream. */

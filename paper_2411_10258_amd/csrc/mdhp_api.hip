@@ -518,8 +518,9 @@ mdhp_status mdhp_warm_start(mdhp_plan* p, const float* pred, const float* mean,
   hipStream_t s = (hipStream_t)stream;
   double* ll_w = p->ll_ws;
   double* ll_c = p->ll_ws + p->W;
-  hipError_t e = warm_params(pred, mean, stdv, p->n, p->T, p->W, p->M, (float)o->mu_floor_rel,
-                             (float)o->beta_floor_rel, mu, alpha, beta, s);
+  hipError_t e = warm_params(pred, mean, stdv, p->counts, p->n, p->T, p->W, p->M,
+                             (float)o->mu_floor_rel, (float)o->beta_floor_rel, mu, alpha, beta,
+                             s);
   if (e == hipSuccess) e = eval_plan(p, mu, alpha, beta, ll_w, nullptr, nullptr, nullptr, s);
   if (e == hipSuccess)
     e = eval_plan(p, mu_cold, alpha_cold, beta_cold, ll_c, nullptr, nullptr, nullptr, s);

@@ -113,8 +113,9 @@ mdhp_status mdhp_fail(mdhp_status s, const std::string& msg);
 mdhp_status mdhp_hip_fail(hipError_t e, const char* where);
 
 hipError_t warm_params(const float* pred, const float* mean, const float* stdv,
-                       const int32_t* n, const double* T, int64_t W, int M, float mu_floor_rel,
-                       float beta_floor_rel, float* mu, float* alpha, float* beta, hipStream_t s);
+                       const int32_t* counts, const int32_t* n, const double* T, int64_t W,
+                       int M, float mu_floor_rel, float beta_floor_rel, float* mu, float* alpha,
+                       float* beta, hipStream_t s);
 hipError_t choose_init(const double* ll_warm, const double* ll_cold, int64_t W, int M,
                        const float* mu_c, const float* al_c, const float* be_c, float* mu,
                        float* alpha, float* beta, int32_t* used_warm, hipStream_t s);

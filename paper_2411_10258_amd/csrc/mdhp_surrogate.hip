@@ -195,11 +195,12 @@ __global__ void to_bf16_kernel(const float* __restrict__ src, __bf16* __restrict
     dst[i] = to_bf16(src[i]);
 }
 
-// Prediction (z-scored log-parameters) -> parameters:
-// mu = exp(y_mu), alpha = exp(y_alpha), beta = exp(y_beta) with
-// y = pred * std + mean, clamped to the projection's floors.
+// Prediction -> parameters: y = pred * std + mean holds, per window,
+// log(mu_m T / max(N_m, 0.5)), the branching entries alpha_mn / beta and
+// log beta; mu and beta are clamped to the projection's floors.
 __global__ void warm_params_kernel(const float* __restrict__ pred, const float* __restrict__ mean,
-                                   const float* __restrict__ stdv, const int32_t* __restrict__ n,
+                                   const float* __restrict__ stdv,
+                                   const int32_t* __restrict__ counts, const int32_t* __restrict__ n,
                                    const double* __restrict__ T, int64_t W, int M,
                                    float mu_floor_rel, float beta_floor_rel, float* __restrict__ mu,
                                    float* __restrict__ alpha, float* __restrict__ beta) {
@@ -208,12 +209,18 @@ __global__ void warm_params_kernel(const float* __restrict__ pred, const float* 
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t w = i / O;
     const int o = (int)(i % O);
-    const float y = pred[i] * stdv[o] + mean[o];
-    const float v = expf(fminf(y, 30.f));
     const float rate = (float)((double)max(n[w], 1) / T[w]);
-    if (o < M) mu[w * M + o] = fmaxf(v, mu_floor_rel * rate);
-    else if (o < M + M * M) alpha[w * M * M + (o - M)] = v;
-    else beta[w] = fmaxf(v, beta_floor_rel * rate);
+    const float yb = pred[w * O + O - 1] * stdv[O - 1] + mean[O - 1];
+    const float b = fmaxf(expf(fminf(yb, 30.f)), beta_floor_rel * rate);
+    const float y = pred[i] * stdv[o] + mean[o];
+    if (o < M) {
+      const float rm = (float)(fmax((double)counts[w * M + o], 0.5) / T[w]);
+      mu[w * M + o] = fmaxf(expf(fminf(y, 30.f)) * rm, mu_floor_rel * rate);
+    } else if (o < M + M * M) {
+      alpha[w * M * M + (o - M)] = fmaxf(y, 0.f) * b;
+    } else {
+      beta[w] = b;
+    }
   }
 }
 
@@ -609,11 +616,12 @@ mdhp_status mdhp_surrogate_train_step(mdhp_surrogate* s, const uint16_t* x, int3
 namespace mdhp {
 
 hipError_t warm_params(const float* pred, const float* mean, const float* stdv,
-                       const int32_t* n, const double* T, int64_t W, int M, float mu_floor_rel,
-                       float beta_floor_rel, float* mu, float* alpha, float* beta, hipStream_t s) {
+                       const int32_t* counts, const int32_t* n, const double* T, int64_t W,
+                       int M, float mu_floor_rel, float beta_floor_rel, float* mu, float* alpha,
+                       float* beta, hipStream_t s) {
   const int64_t total = W * (int64_t)(M + M * M + 1);
   hipLaunchKernelGGL(warm_params_kernel, dim3(grid_for(total)), dim3(256), 0, s, pred, mean, stdv,
-                     n, T, W, M, mu_floor_rel, beta_floor_rel, mu, alpha, beta);
+                     counts, n, T, W, M, mu_floor_rel, beta_floor_rel, mu, alpha, beta);
   return hipGetLastError();
 }
 

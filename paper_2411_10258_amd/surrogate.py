@@ -8,8 +8,12 @@ kernel, the BF16 MFMA GEMMs of the forward and backward passes, the loss,
 Adam, and the warm-start epilogue.  This module marshals arguments and
 organises training (mini-batches, target normalisation).
 
-Targets (per window, in parameter layout order): log mu, log max(alpha,
-1e-3 beta), log beta, z-scored per output over the training set.
+Targets (per window, in parameter layout order): log(mu_m T / max(N_m,
+0.5)) (mu over the window's rate of dimension m), the branching entries
+alpha_mn / beta, and log beta, z-scored per output over the training set.
+The branching entries are regressed in linear scale, so that the
+prediction keeps their mean (and the total excitation) rather than a
+geometric mean pulled to 0 by the many entries a fit leaves at the bound.
 Inputs: log1p(count * bins / T) for 64 equal bins per dimension.
 """
 
@@ -44,14 +48,25 @@ def features(offsets, t, dim, T, M: int, bins: int = BINS, device="cuda", stream
     return x
 
 
-def log_targets(M: int, mu, alpha, beta) -> np.ndarray:
-    """[W, M + M*M + 1] = (log mu, log max(alpha, 1e-3 beta), log beta)."""
+def dim_counts(offsets, dim, M: int) -> np.ndarray:
+    """[W, M] events per window and dimension (host arrays)."""
+    offsets = np.asarray(offsets, np.int64)
+    W = len(offsets) - 1
+    w = np.repeat(np.arange(W), np.diff(offsets))
+    Nm = np.zeros((W, M), np.float64)
+    np.add.at(Nm, (w, np.asarray(dim)), 1.0)
+    return Nm
+
+
+def log_targets(M: int, mu, alpha, beta, Nm, T) -> np.ndarray:
+    """[W, M + M*M + 1] = (log(mu T / max(N_m, 0.5)), alpha / beta, log beta)."""
     mu = np.asarray(mu, np.float64)
     alpha = np.asarray(alpha, np.float64)
     beta = np.asarray(beta, np.float64)
     W = mu.shape[0]
-    a = np.maximum(alpha.reshape(W, M * M), 1e-3 * beta[:, None])
-    return np.concatenate([np.log(mu), np.log(a), np.log(beta)[:, None]], axis=1)
+    rate = np.maximum(np.asarray(Nm, np.float64), 0.5) / np.asarray(T, np.float64)[:, None]
+    return np.concatenate([np.log(mu / rate), alpha.reshape(W, M * M) / beta[:, None],
+                           np.log(beta)[:, None]], axis=1)
 
 
 @dataclass

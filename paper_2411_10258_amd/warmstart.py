@@ -23,7 +23,8 @@ import torch
 import synth
 
 from .api import BETA_SHARED, FIT_CONVERGED, FIT_STALLED, OPT_LBFGS, FitOptions, Plan
-from .surrogate import BINS, Surrogate, TargetStats, features, log_targets, warm_start
+from .surrogate import (BINS, Surrogate, TargetStats, dim_counts, features, log_targets,
+                        warm_start)
 
 DEFAULT_FIT = dict(max_steps=1000, optimizer=OPT_LBFGS, ll_tol=1e-7, history=8)
 
@@ -87,7 +88,8 @@ def build_training_set(M: int, n_windows: int, seed: int = 1024, chunk: int = 40
         fit_s += t2 - t1
         stat = stat.cpu().numpy()
         xs.append(features(db.offsets, db.t, db.dim, db.T, M))
-        ys.append(log_targets(M, mu.cpu().numpy(), al.cpu().numpy(), be.cpu().numpy()))
+        ys.append(log_targets(M, mu.cpu().numpy(), al.cpu().numpy(), be.cpu().numpy(),
+                              dim_counts(b.offsets, b.dim, M), b.T))
         oks.append((stat == FIT_CONVERGED) | (stat == FIT_STALLED))
         if log:
             log(f"training windows {first + W}/{n_windows}: sim {t1 - t0:.1f}s fit {t2 - t1:.2f}s")

@@ -51,7 +51,8 @@ def test_graph_warm_padam_m16(gpu, synth_lib):
     b = synth_lib.batch_m16(W=64)
     print(f"[graph] warm projected Adam M=16 W={b.W}", flush=True)
     net = surrogate.Surrogate(16, hidden=512, max_batch=64, seed=11)
-    y = surrogate.log_targets(16, b.mu, b.alpha, b.beta)
+    Nm = surrogate.dim_counts(b.offsets, b.dim, 16)
+    y = surrogate.log_targets(16, b.mu, b.alpha, b.beta, Nm, b.T)
     net.stats = surrogate.TargetStats.fit(y)
     plan = gpu.Plan(b.offsets, b.t, b.dim, b.T, b.M, 0)
     opts = gpu.FitOptions(max_steps=40, optimizer=gpu.OPT_PADAM, lr=3e-2, ll_tol=1e-7)

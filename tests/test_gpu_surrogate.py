@@ -97,7 +97,8 @@ def test_warm_start_falls_back_to_cold(gpu, oracle_lib, synth_lib):
     net = _net(gpu, seed=9, max_batch=64)
     x = surrogate.features(b.offsets, b.t, b.dim, b.T, M)
     # Targets at the truth for even windows; nonsense (huge alpha) for odd ones.
-    y = surrogate.log_targets(M, b.mu, b.alpha, b.beta)
+    y = surrogate.log_targets(M, b.mu, b.alpha, b.beta,
+                              surrogate.dim_counts(b.offsets, b.dim, M), b.T)
     stats = surrogate.TargetStats.fit(y)
     pred_true = torch.from_numpy(stats.normalize(y)).cuda()
     plan = gpu.Plan(b.offsets, b.t, b.dim, b.T, M, 0)
@@ -112,7 +113,7 @@ def test_warm_start_falls_back_to_cold(gpu, oracle_lib, synth_lib):
     from paper_2411_10258_amd.api import _ptr
     pred = pred_true.clone()
     bad = np.arange(b.W) % 2 == 1
-    pred[torch.from_numpy(bad).cuda(), M:M + M * M] = 50.0  # exp(50 std + mean): explosive alpha
+    pred[torch.from_numpy(bad).cuda(), M:M + M * M] = 50.0  # 50 std + mean: explosive alpha
     mean = torch.from_numpy(stats.mean).cuda()
     std = torch.from_numpy(stats.std).cuda()
     mu = torch.empty(b.W, M, device="cuda")
@@ -131,9 +132,10 @@ def test_warm_start_falls_back_to_cold(gpu, oracle_lib, synth_lib):
     assert np.all(used[bad] == 0)
     assert np.all(used[~bad] == 1)
     assert np.allclose(alpha.cpu().numpy()[bad], al_c[bad])
-    # The warm windows start at the (clipped) truth.
-    a_true = np.maximum(b.alpha, 1e-3 * b.beta[:, None, None])
-    assert np.allclose(alpha.cpu().numpy()[~bad], a_true[~bad], rtol=1e-4)
+    # The warm windows start at the truth.
+    assert np.allclose(alpha.cpu().numpy()[~bad], b.alpha[~bad], rtol=1e-4, atol=1e-6)
+    assert np.allclose(mu.cpu().numpy()[~bad], b.mu[~bad], rtol=1e-4)
+    assert np.allclose(beta.cpu().numpy()[~bad], b.beta[~bad], rtol=1e-4)
     plan.close()
     net.close()
 
