@@ -17,6 +17,8 @@ windows; the paper's own dataset is not used):
                       5,000 events each
 * ``large_m64``       16,384 windows, M=64, shared decay, log-normal counts
                       (median 5,000, sigma 1.2, clipped to [500, 50,000])
+* ``streams_m16``     1,024 event streams, M=16, parameters as batch_m16's,
+                      2,304 events each (for sliding windows)
 """
 
 from __future__ import annotations
@@ -224,6 +226,18 @@ def large_m64(W: int = 16384, seed: int = 2024, first: int = 0, nthreads: int = 
                                            (0.5, 1.0, 2.0), 5000.0, 1.2, 500, 50000)
     off, t, d, T = _simulate_windows(64, 0, mu, alpha, beta, counts, seed, windows, nthreads)
     return Batch(64, 0, off, t, d, T, mu, alpha, beta, name="large_m64")
+
+
+def streams_m16(S: int = 1024, n_events: int = 2304, seed: int = 2025, nthreads: int = 0) -> Batch:
+    """S long M=16 event streams (one per sender), parameters drawn like the
+    M=16 batch workload's (one decay per stream in {0.5, 1, 2}), n_events
+    events each: the input of sliding-window fitting."""
+    streams = np.arange(S)
+    mu, alpha, beta, _ = _draw_shared(seed, streams, 16, 0.05, 1.0, 0.2, 0.8,
+                                      (0.5, 1.0, 2.0), 1000.0, 1.0, 100, 20000)
+    counts = np.full(S, n_events, np.int64)
+    off, t, d, T = _simulate_windows(16, 0, mu, alpha, beta, counts, seed, streams, nthreads)
+    return Batch(16, 0, off, t, d, T, mu, alpha, beta, name="streams_m16")
 
 
 def pair_m32(W: int = 1024, seed: int = 2024, first: int = 0, n_events: int = 5000,
