@@ -829,13 +829,40 @@ __device__ __forceinline__ double block_max_abs(double v, double* scratch) {
   return fmax(fmax(scratch[0], scratch[1]), fmax(scratch[2], scratch[3]));
 }
 
+// L-BFGS vectors of one workgroup in the global workspace: vector v, slot k
+// of thread tid at float (v * K + k) * kBlock + tid, so that one wavefront's
+// access to a slot is 256 contiguous bytes.  Vectors 0..2 are x, g and d of
+// the current iteration (kept for the evaluations of the line search), then
+// the history pairs s_j (3 + j) and y_j (3 + kMaxHistory + j).  Buffer
+// loads and stores with the thread's byte offset in one register and the
+// slot's in a scalar: no per-slot address registers.
+constexpr int kLbfgsVectors = 3 + 2 * kMaxHistory;
+
+template <int K>
+struct LbfgsWs {
+  __amdgpu_buffer_rsrc_t r;
+  int voff;
+  __device__ LbfgsWs(float* ws) {
+    float* base = ws + (size_t)blockIdx.x * ((size_t)kLbfgsVectors * K * kBlock);
+    r = __builtin_amdgcn_make_buffer_rsrc(base, 0, kLbfgsVectors * K * kBlock * 4, 0x00020000);
+    voff = threadIdx.x * 4;
+  }
+  __device__ float ld(int v, int k) const {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, (v * K + k) * kBlock * 4, 0));
+  }
+  __device__ void st(int v, int k, float x) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, voff, (v * K + k) * kBlock * 4, 0);
+  }
+};
+
 // Projected L-BFGS fit (the update rule is described with the options in
 // the public header).  Thread tid owns parameter slots k < OWN: alpha
 // entry e = tid + k * kBlock (row e / P, column e % P), and slot OWN: mu_tid
-// (tid < M) or beta (tid == M).  Its slices of x, g, d and of the history
-// pairs live in a per-workgroup region of the global workspace that only it
-// reads and writes; the scalars of the two-loop recursion come from block
-// reductions.
+// (tid < M) or beta (tid == M).  Between evaluations its slices of x, g and
+// of the direction are in registers; x, g and d go to the workspace before
+// the line search (whose evaluations need every register) and are read back
+// by each trial and by the update; the history pairs live there.  The scalars of the two-loop
+// recursion come from block reductions.
 template <int P, int SB>
 __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_lbfgs_kernel(Events ev, int M, FitParams o,
                                                               float* mu, float* alpha,
@@ -849,19 +876,13 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_lbf
   __shared__ int flag;
   constexpr int OWN = own_count(P);
   constexpr int K = OWN + 1;
+  constexpr int VX = 0, VG = 1, VD = 2;
   double gR64[OWN];
   const int tid = threadIdx.x;
   const int m_hist = o.history;
-  // Workspace of this workgroup: X, G, D, XN then S[m], Y[m]; slot (k, tid).
-  float* base = ws + (size_t)blockIdx.x * (size_t)(4 + 2 * kMaxHistory) * K * kBlock;
-  auto X = [&](int k) -> float& { return base[(0 * K + k) * kBlock + tid]; };
-  auto Gv = [&](int k) -> float& { return base[(1 * K + k) * kBlock + tid]; };
-  auto D = [&](int k) -> float& { return base[(2 * K + k) * kBlock + tid]; };
-  auto XN = [&](int k) -> float& { return base[(3 * K + k) * kBlock + tid]; };
-  auto Sv = [&](int j, int k) -> float& { return base[((4 + j) * K + k) * kBlock + tid]; };
-  auto Yv = [&](int j, int k) -> float& {
-    return base[((4 + kMaxHistory + j) * K + k) * kBlock + tid];
-  };
+  const LbfgsWs<K> wsp(ws);
+  auto VS = [](int j) { return 3 + j; };
+  auto VY = [](int j) { return 3 + kMaxHistory + j; };
   init_lds(sh);
   for (int q = next_window(sh, counter, 1); q < ev.W; q = next_window(sh, counter, 0)) {
     const int64_t w = ev.order[q];
@@ -886,6 +907,7 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_lbf
       const int kd = kind(k);
       return kd == 2 ? mu_min : (kd == 3 ? beta_min : 0.f);
     };
+    // Current parameter of slot k (zero for slots that hold none).
     auto get_param = [&](int k) -> float {
       const int kd = kind(k);
       if (kd == 1) return sh.A(tid + k * kBlock);
@@ -937,23 +959,28 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_lbf
     } else {
       l = sh.scal[0];
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        X(k) = get_param(k);
-        Gv(k) = (float)grad_f(k);
-      }
+      for (int k = 0; k < K; ++k) wsp.st(VG, k, (float)grad_f(k));
       double f = -l * inv_n;
       for (s = 0;; ++s) {
         if (s == o.max_steps) {
           st = MDHP_FIT_MAX_STEPS;
           break;
         }
+        // Current point and active set: a slot is held when it holds no
+        // parameter or sits at its bound with the gradient pushing out.
+        float xk[K], gk[K];
+        unsigned act = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          xk[k] = get_param(k);
+          gk[k] = wsp.ld(VG, k);
+          if (kind(k) == 0 || (xk[k] <= lower(k) && gk[k] > 0.f)) act |= 1u << k;
+        }
         // Free gradient and its largest entry.
         double qv[K], gmax_local = 0.0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const float g = Gv(k);
-          const bool active = kind(k) == 0 || (X(k) <= lower(k) && g > 0.f);
-          qv[k] = active ? 0.0 : (double)g;
+          qv[k] = (act >> k) & 1 ? 0.0 : (double)gk[k];
           gmax_local = fmax(gmax_local, fabs(qv[k]));
         }
         const double gmax = block_max_abs(gmax_local, scratch);
@@ -964,49 +991,64 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_lbf
         const double gamma0 = 0.01 / gmax;
         for (int i = 0; i < h; ++i) {
           const int j = (head - 1 - i + m_hist) % m_hist;
+          float sj[K], yj[K];
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            sj[k] = wsp.ld(VS(j), k);
+            yj[k] = wsp.ld(VY(j), k);
+          }
           double v[1] = {0.0};
 #pragma unroll
-          for (int k = 0; k < K; ++k) v[0] += (double)Sv(j, k) * qv[k];
+          for (int k = 0; k < K; ++k) v[0] += (double)sj[k] * qv[k];
           block_sums<1>(v, scratch);
           const double a = rho_s[j] * v[0];
           if (tid == 0) a_s[j] = a;
 #pragma unroll
-          for (int k = 0; k < K; ++k) qv[k] -= a * (double)Yv(j, k);
+          for (int k = 0; k < K; ++k) qv[k] -= a * (double)yj[k];
         }
         const double gamma = h > 0 ? sy_new / yy_new : gamma0;
 #pragma unroll
         for (int k = 0; k < K; ++k) qv[k] *= gamma;
         for (int i = h - 1; i >= 0; --i) {
           const int j = (head - 1 - i + m_hist) % m_hist;
+          float sj[K], yj[K];
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            yj[k] = wsp.ld(VY(j), k);
+            sj[k] = wsp.ld(VS(j), k);
+          }
           double v[1] = {0.0};
 #pragma unroll
-          for (int k = 0; k < K; ++k) v[0] += (double)Yv(j, k) * qv[k];
+          for (int k = 0; k < K; ++k) v[0] += (double)yj[k] * qv[k];
           block_sums<1>(v, scratch);
           const double b = rho_s[j] * v[0];
           const double a = a_s[j];
 #pragma unroll
-          for (int k = 0; k < K; ++k) qv[k] += (a - b) * (double)Sv(j, k);
+          for (int k = 0; k < K; ++k) qv[k] += (a - b) * (double)sj[k];
         }
+        float dk[K];
         double dg[1] = {0.0};
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const float g = Gv(k);
-          const bool active = kind(k) == 0 || (X(k) <= lower(k) && g > 0.f);
-          const double dk = active ? 0.0 : -qv[k];
-          D(k) = (float)dk;
-          dg[0] += dk * (double)g;
+          const double dd = (act >> k) & 1 ? 0.0 : -qv[k];
+          dk[k] = (float)dd;
+          dg[0] += dd * (double)gk[k];
         }
         block_sums<1>(dg, scratch);
         if (!(dg[0] < 0.0)) {  // restart from scaled steepest descent
           h = 0;
 #pragma unroll
-          for (int k = 0; k < K; ++k) {
-            const float g = Gv(k);
-            const bool active = kind(k) == 0 || (X(k) <= lower(k) && g > 0.f);
-            D(k) = active ? 0.f : (float)(-gamma0 * (double)g);
-          }
+          for (int k = 0; k < K; ++k)
+            dk[k] = (act >> k) & 1 ? 0.f : (float)(-gamma0 * (double)gk[k]);
         }
-        // Backtracking line search on the projected path.
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          wsp.st(VX, k, xk[k]);
+          wsp.st(VD, k, dk[k]);
+        }
+        // Backtracking line search on the projected path.  Every trial reads
+        // x, g and d back from the workspace, so that none of them is held in
+        // registers across an evaluation.
         double t = 1.0, ln = 0.0, fn = 0.0;
         bool ok = false;
         for (int ls = 0; ls < 20 && !ok; ++ls, t *= 0.5) {
@@ -1014,11 +1056,10 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_lbf
 #pragma unroll
           for (int k = 0; k < K; ++k) {
             if (kind(k) == 0) continue;
-            const float x0 = X(k);
-            const float xn = fmaxf((float)((double)x0 + t * (double)D(k)), lower(k));
-            XN(k) = xn;
+            const float x0 = wsp.ld(VX, k);
+            const float xn = fmaxf((float)((double)x0 + t * (double)wsp.ld(VD, k)), lower(k));
             set_param(k, xn);
-            dec[0] += (double)Gv(k) * ((double)xn - (double)x0);
+            dec[0] += (double)wsp.ld(VG, k) * ((double)xn - (double)x0);
           }
           block_sums<1>(dec, scratch);
           refresh_colsum();
@@ -1031,31 +1072,32 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_lbf
         if (!ok) {
           st = MDHP_FIT_STALLED;
 #pragma unroll
-          for (int k = 0; k < K; ++k) set_param(k, X(k));
+          for (int k = 0; k < K; ++k) set_param(k, wsp.ld(VX, k));
           __syncthreads();
           break;
         }
+        // New pair s = x' - x, y = g' - g; x' is the accepted point in LDS.
         double sums[3] = {0.0, 0.0, 0.0};  // s.y, s.s, y.y
         float sk[K], yk[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           const float gn = (float)grad_f(k);
-          const float xn = kind(k) == 0 ? X(k) : XN(k);
-          sk[k] = xn - X(k);
-          yk[k] = gn - Gv(k);
+          const float x0 = wsp.ld(VX, k);
+          const float xn = kind(k) == 0 ? x0 : get_param(k);
+          sk[k] = xn - x0;
+          yk[k] = gn - wsp.ld(VG, k);
+          wsp.st(VG, k, gn);  // g' replaces g (read by the next iteration)
           sums[0] += (double)sk[k] * (double)yk[k];
           sums[1] += (double)sk[k] * (double)sk[k];
           sums[2] += (double)yk[k] * (double)yk[k];
-          X(k) = xn;
-          Gv(k) = gn;
         }
         block_sums<3>(sums, scratch);
         if (sums[0] > 1e-10 * sqrt(sums[1] * sums[2])) {
           if (h == m_hist) h -= 1;  // the oldest pair drops out of the ring
 #pragma unroll
           for (int k = 0; k < K; ++k) {
-            Sv(head, k) = sk[k];
-            Yv(head, k) = yk[k];
+            wsp.st(VS(head), k, sk[k]);
+            wsp.st(VY(head), k, yk[k]);
           }
           if (tid == 0) rho_s[head] = 1.0 / sums[0];
           sy_new = sums[0];
@@ -1114,7 +1156,7 @@ hipError_t launch_shared_fit(const Events& ev, int M, const FitParams& o, float*
   reset_counter(counter, s);
   if (o.optimizer == MDHP_OPT_LBFGS) {
     auto k = shared_lbfgs_kernel<P, SB>;
-    const int64_t per_block = (int64_t)(4 + 2 * kMaxHistory) * (own_count(P) + 1) * kBlock;
+    const int64_t per_block = (int64_t)kLbfgsVectors * (own_count(P) + 1) * kBlock;
     const int grid = (int)std::min<int64_t>(occupancy_grid(k, kBlock, ev.W), ws_floats / per_block);
     if (grid < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), 0, s, ev, M, o, mu, alpha, beta, ll, steps,
@@ -1129,7 +1171,7 @@ hipError_t launch_shared_fit(const Events& ev, int M, const FitParams& o, float*
 
 template <int P, int SB>
 int64_t shared_lbfgs_ws(int64_t W) {
-  const int64_t per_block = (int64_t)(4 + 2 * kMaxHistory) * (own_count(P) + 1) * kBlock;
+  const int64_t per_block = (int64_t)kLbfgsVectors * (own_count(P) + 1) * kBlock;
   return per_block * occupancy_grid(shared_lbfgs_kernel<P, SB>, kBlock, std::max<int64_t>(W, 1));
 }
 
