@@ -170,6 +170,34 @@ __device__ __forceinline__ float group_scan(float v, int lane) {
   return v;
 }
 
+// L-BFGS vectors of one team (T threads, K parameter slots per thread) in
+// the global workspace: vector v, slot k of team thread t at float
+// (v * K + k) * T + t, so that one wavefront's access to a slot is 256
+// contiguous bytes.  Vectors 0..2 are x, g and d of the current iteration,
+// then the history pairs s_j (3 + j) and y_j (3 + kMaxHistory + j).  Buffer
+// loads and stores with the thread's byte offset in one register and the
+// slot's in a scalar: no per-slot address registers.  `base` must be the
+// same for every thread of the team.
+constexpr int kLbfgsVectors = 3 + 2 * kMaxHistory;
+
+template <int K, int T>
+struct LbfgsWs {
+  __amdgpu_buffer_rsrc_t r;
+  int voff;
+  __device__ LbfgsWs(float* base, int t) {
+    r = __builtin_amdgcn_make_buffer_rsrc(base, 0, kLbfgsVectors * K * T * 4, 0x00020000);
+    voff = t * 4;
+  }
+  __device__ float ld(int v, int k) const {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, (v * K + k) * T * 4, 0));
+  }
+  __device__ void st(int v, int k, float x) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, voff, (v * K + k) * T * 4, 0);
+  }
+  static constexpr int X = 0, G = 1, D = 2;
+  static constexpr int S(int j) { return 3 + j; }
+  static constexpr int Y(int j) { return 3 + kMaxHistory + j; }
+};
 
 template <class K>
 int occupancy_grid(K kernel, int threads, int64_t W) {

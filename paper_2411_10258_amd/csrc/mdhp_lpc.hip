@@ -934,11 +934,11 @@ __global__ __launch_bounds__(kLpcBlock, kMinBlocksLpc) void lpc_fit_kernel(Event
       });
 }
 
-// Workspace floats of one team's L-BFGS fit: X, G, D, XN, then the S and Y
+// Workspace floats of one team's L-BFGS fit: x, g, d, then the s and y
 // rings; K slots of T lanes each.
 template <int MP, int NW>
 constexpr int64_t team_ws() {
-  return (int64_t)(4 + 2 * kMaxHistory) * Slots<MP, NW>::K * 64 * NW;
+  return (int64_t)kLbfgsVectors * Slots<MP, NW>::K * 64 * NW;
 }
 
 // Per workgroup: the larger of one big team and kWaves small teams.
@@ -951,7 +951,10 @@ constexpr int64_t block_ws() {
 // Projected L-BFGS on one window: the rule of the workgroup kernel (two-loop
 // recursion on the free set, Armijo backtracking on the projected path,
 // curvature-checked history, restart from scaled steepest descent) with
-// team-level reductions.
+// team-level reductions.  Between evaluations the lane's slices of x, g and
+// the direction are in registers; x, g and d go to the team's workspace
+// (base: the same for the whole team) for the line search, whose
+// evaluations need every register.
 template <int MP, int NW>
 __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, int64_t w, int M,
                                           const FitParams& o, float* mu, float* alpha,
@@ -959,17 +962,11 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
                                           int* evals_out, float* base) {
   constexpr int K = Slots<MP, NW>::K;
   constexpr int T = Team<MP, NW>::T;
+  using Ws = LbfgsWs<K, T>;
   const int t = team_tid<NW>();
   const int m_hist = o.history;
   const Slots<MP, NW> sl{M, t, o.fix_beta};
-  auto X = [&](int k) -> float& { return base[(0 * K + k) * T + t]; };
-  auto Gv = [&](int k) -> float& { return base[(1 * K + k) * T + t]; };
-  auto Dv = [&](int k) -> float& { return base[(2 * K + k) * T + t]; };
-  auto XN = [&](int k) -> float& { return base[(3 * K + k) * T + t]; };
-  auto Sv = [&](int j, int k) -> float& { return base[((4 + j) * K + k) * T + t]; };
-  auto Yv = [&](int j, int k) -> float& {
-    return base[((4 + kMaxHistory + j) * K + k) * T + t];
-  };
+  const Ws wsp(base, t);
   team_load(sh, mu, alpha, beta, w, M);
   const int n = ev.n[w];
   const double Tw = ev.T[w];
@@ -1002,24 +999,26 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
     l = uni(sh.scal[0]);
   } else {
     l = uni(sh.scal[0]);
+    float gk[K];  // gradient at the current point
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      X(k) = sl.get(sh, k);
-      Gv(k) = (float)gf(k);
-    }
+    for (int k = 0; k < K; ++k) gk[k] = (float)gf(k);
     double f = -l * inv_n;
     for (s = 0;; ++s) {
       if (s == o.max_steps) {
         st = MDHP_FIT_MAX_STEPS;
         break;
       }
-      // Free gradient and its largest entry.
+      // Current point (the LDS parameters) and active set: a slot is held
+      // when it holds no parameter or sits at its bound with the gradient
+      // pushing out.  Free gradient and its largest entry.
+      float xk[K];
+      unsigned act = 0;
       double qv[K], gmax_l = 0.0;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const float g = Gv(k);
-        const bool active = sl.kind(k) == 0 || (X(k) <= lower(k) && g > 0.f);
-        qv[k] = active ? 0.0 : (double)g;
+        xk[k] = sl.get(sh, k);
+        if (sl.kind(k) == 0 || (xk[k] <= lower(k) && gk[k] > 0.f)) act |= 1u << k;
+        qv[k] = (act >> k) & 1 ? 0.0 : (double)gk[k];
         gmax_l = fmax(gmax_l, fabs(qv[k]));
       }
       const double gmax = team_max(sh, gmax_l);
@@ -1028,13 +1027,14 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
         break;
       }
       const double gamma0 = 0.01 / gmax;
+      const double gamma = h > 0 ? sy_new / yy_new : gamma0;
       for (int i = 0; i < h; ++i) {
         const int j = (head - 1 - i + m_hist) % m_hist;
         float sj[K], yj[K];  // both loads in flight together
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          sj[k] = Sv(j, k);
-          yj[k] = Yv(j, k);
+          sj[k] = wsp.ld(Ws::S(j), k);
+          yj[k] = wsp.ld(Ws::Y(j), k);
         }
         double v = 0.0;
 #pragma unroll
@@ -1044,7 +1044,6 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
 #pragma unroll
         for (int k = 0; k < K; ++k) qv[k] -= a * (double)yj[k];
       }
-      const double gamma = h > 0 ? sy_new / yy_new : gamma0;
 #pragma unroll
       for (int k = 0; k < K; ++k) qv[k] *= gamma;
       team_sync<NW>();
@@ -1053,8 +1052,8 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
         float sj[K], yj[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          sj[k] = Sv(j, k);
-          yj[k] = Yv(j, k);
+          sj[k] = wsp.ld(Ws::S(j), k);
+          yj[k] = wsp.ld(Ws::Y(j), k);
         }
         double v = 0.0;
 #pragma unroll
@@ -1064,26 +1063,29 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
 #pragma unroll
         for (int k = 0; k < K; ++k) qv[k] += (a - bcoef) * (double)sj[k];
       }
+      float dk[K];
       double dg = 0.0;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const float g = Gv(k);
-        const bool active = sl.kind(k) == 0 || (X(k) <= lower(k) && g > 0.f);
-        const double dk = active ? 0.0 : -qv[k];
-        Dv(k) = (float)dk;
-        dg += dk * (double)g;
+        const double dd = (act >> k) & 1 ? 0.0 : -qv[k];
+        dk[k] = (float)dd;
+        dg += dd * (double)gk[k];
       }
       dg = team_sum(sh, dg);
       if (!(dg < 0.0)) {  // restart from scaled steepest descent
         h = 0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float g = Gv(k);
-          const bool active = sl.kind(k) == 0 || (X(k) <= lower(k) && g > 0.f);
-          Dv(k) = active ? 0.f : (float)(-gamma0 * (double)g);
-        }
+        for (int k = 0; k < K; ++k)
+          dk[k] = (act >> k) & 1 ? 0.f : (float)(-gamma0 * (double)gk[k]);
       }
-      // Backtracking line search on the projected path.
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        wsp.st(Ws::X, k, xk[k]);
+        wsp.st(Ws::G, k, gk[k]);
+        wsp.st(Ws::D, k, dk[k]);
+      }
+      // Backtracking line search on the projected path; every trial reads
+      // x, g and d back from the workspace.
       double step = 1.0, ln = 0.0, fn = 0.0;
       bool ok = false;
       for (int ls = 0; ls < 20 && !ok; ++ls, step *= 0.5) {
@@ -1092,11 +1094,10 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           if (sl.kind(k) == 0) continue;
-          const float x0 = X(k);
-          const float xn = fmaxf((float)((double)x0 + step * (double)Dv(k)), lower(k));
-          XN(k) = xn;
+          const float x0 = wsp.ld(Ws::X, k);
+          const float xn = fmaxf((float)((double)x0 + step * (double)wsp.ld(Ws::D, k)), lower(k));
           sl.set(sh, k, xn);
-          dec += (double)Gv(k) * ((double)xn - (double)x0);
+          dec += (double)wsp.ld(Ws::G, k) * ((double)xn - (double)x0);
         }
         dec = team_sum(sh, dec);
         team_colsum(sh, M);
@@ -1110,23 +1111,24 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
         st = MDHP_FIT_STALLED;
         team_sync<NW>();
 #pragma unroll
-        for (int k = 0; k < K; ++k) sl.set(sh, k, X(k));
+        for (int k = 0; k < K; ++k) sl.set(sh, k, wsp.ld(Ws::X, k));
         team_sync<NW>();
         break;
       }
+      // New pair s = x' - x, y = g' - g; x' is the accepted point in LDS.
       double sy = 0.0, ss = 0.0, yy = 0.0;
       float sk[K], yk[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const float gn = (float)gf(k);
-        const float xn = sl.kind(k) == 0 ? X(k) : XN(k);
-        sk[k] = xn - X(k);
-        yk[k] = gn - Gv(k);
+        const float x0 = wsp.ld(Ws::X, k);
+        const float xn = sl.kind(k) == 0 ? x0 : sl.get(sh, k);
+        sk[k] = xn - x0;
+        yk[k] = gn - wsp.ld(Ws::G, k);
         sy += (double)sk[k] * (double)yk[k];
         ss += (double)sk[k] * (double)sk[k];
         yy += (double)yk[k] * (double)yk[k];
-        X(k) = xn;
-        Gv(k) = gn;
+        gk[k] = gn;
       }
       team_sum2(sh, sy, ss);
       yy = team_sum(sh, yy);
@@ -1134,8 +1136,8 @@ __device__ __forceinline__ void lbfgs_one(Team<MP, NW>& sh, const Events& ev, in
         if (h == m_hist) h -= 1;  // the oldest pair drops out of the ring
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          Sv(head, k) = sk[k];
-          Yv(head, k) = yk[k];
+          wsp.st(Ws::S(head), k, sk[k]);
+          wsp.st(Ws::Y(head), k, yk[k]);
         }
         if (t == 0) sh.rho[head] = 1.0 / sy;
         sy_new = sy;
@@ -1181,7 +1183,8 @@ __global__ __launch_bounds__(kLpcBlock, kMinBlocksLpc) void lpc_lbfgs_kernel(Eve
       },
       [&](Team<MP, 1>& sh, int64_t w) {
         lbfgs_one<MP, 1>(sh, ev, w, M, o, mu, alpha, beta, ll, steps, status, evals_out,
-                         blk + (size_t)(threadIdx.x >> 6) * (size_t)team_ws<MP, 1>());
+                         blk + (size_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) *
+                                   (size_t)team_ws<MP, 1>());
       });
 }
 

@@ -829,32 +829,6 @@ __device__ __forceinline__ double block_max_abs(double v, double* scratch) {
   return fmax(fmax(scratch[0], scratch[1]), fmax(scratch[2], scratch[3]));
 }
 
-// L-BFGS vectors of one workgroup in the global workspace: vector v, slot k
-// of thread tid at float (v * K + k) * kBlock + tid, so that one wavefront's
-// access to a slot is 256 contiguous bytes.  Vectors 0..2 are x, g and d of
-// the current iteration (kept for the evaluations of the line search), then
-// the history pairs s_j (3 + j) and y_j (3 + kMaxHistory + j).  Buffer
-// loads and stores with the thread's byte offset in one register and the
-// slot's in a scalar: no per-slot address registers.
-constexpr int kLbfgsVectors = 3 + 2 * kMaxHistory;
-
-template <int K>
-struct LbfgsWs {
-  __amdgpu_buffer_rsrc_t r;
-  int voff;
-  __device__ LbfgsWs(float* ws) {
-    float* base = ws + (size_t)blockIdx.x * ((size_t)kLbfgsVectors * K * kBlock);
-    r = __builtin_amdgcn_make_buffer_rsrc(base, 0, kLbfgsVectors * K * kBlock * 4, 0x00020000);
-    voff = threadIdx.x * 4;
-  }
-  __device__ float ld(int v, int k) const {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, (v * K + k) * kBlock * 4, 0));
-  }
-  __device__ void st(int v, int k, float x) const {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, voff, (v * K + k) * kBlock * 4, 0);
-  }
-};
-
 // Projected L-BFGS fit (the update rule is described with the options in
 // the public header).  Thread tid owns parameter slots k < OWN: alpha
 // entry e = tid + k * kBlock (row e / P, column e % P), and slot OWN: mu_tid
@@ -880,9 +854,10 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_lbf
   double gR64[OWN];
   const int tid = threadIdx.x;
   const int m_hist = o.history;
-  const LbfgsWs<K> wsp(ws);
-  auto VS = [](int j) { return 3 + j; };
-  auto VY = [](int j) { return 3 + kMaxHistory + j; };
+  const LbfgsWs<K, kBlock> wsp(ws + (size_t)blockIdx.x * ((size_t)kLbfgsVectors * K * kBlock),
+                               tid);
+  auto VS = [](int j) { return LbfgsWs<K, kBlock>::S(j); };
+  auto VY = [](int j) { return LbfgsWs<K, kBlock>::Y(j); };
   init_lds(sh);
   for (int q = next_window(sh, counter, 1); q < ev.W; q = next_window(sh, counter, 0)) {
     const int64_t w = ev.order[q];
