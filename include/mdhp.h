@@ -68,9 +68,11 @@ enum {
 enum { MDHP_BETA_SHARED = 0, MDHP_BETA_PAIR = 1 };
 
 /* Update rules of mdhp_fit_batch (the paper optimises with an unnamed
- * PyTorch optimizer; these are the rules this library offers).
- * MDHP_OPT_LBFGS is available with one decay per window. */
-enum { MDHP_OPT_PGD = 0, MDHP_OPT_PADAM = 1, MDHP_OPT_LBFGS = 2 };
+ * PyTorch optimizer; these are the rules this library offers; the paper
+ * names expectation-maximisation among the estimators of related work).
+ * MDHP_OPT_LBFGS is available with one decay per window, MDHP_OPT_EM with
+ * fix_beta. */
+enum { MDHP_OPT_PGD = 0, MDHP_OPT_PADAM = 1, MDHP_OPT_LBFGS = 2, MDHP_OPT_EM = 3 };
 
 /* Per-window outcome of mdhp_fit_batch.  STALLED: the L-BFGS line search
  * accepted no step (the likelihood no longer increases measurably). */
@@ -125,6 +127,21 @@ typedef struct mdhp_batch {
  * as MAX_STEPS after max_steps accepted steps, and as STALLED when no trial
  * is accepted.  lr, adam_* are not used.
  *
+ * EM (expectation-maximisation on the branching structure: every event is
+ * either a background event of its dimension or the offspring of one
+ * earlier event): the decays stay at their initial values (fix_beta must be
+ * set).  Step s evaluates ll_s, stops as PGD does, and otherwise sets
+ *   mu_m    <- max(mu_m * G_m / T_w, mu_floor_rel * r_w),
+ *   alpha_mn <- alpha_mn * G_mn / C_mn   (unchanged where C_mn = 0),
+ * where G_m = sum_{i: d_i = m} 1 / lambda_i (mu_m G_m is the expected number
+ * of background events of dimension m), G_mn = sum_{i: d_i = m} R_mn(i) /
+ * lambda_i (alpha_mn G_mn: the expected number of dimension-m events
+ * triggered by dimension-n events) and C_mn = sum_{k: d_k = n}
+ * (1 - e^{-beta_mn (T_w - t_k)}) / beta_mn (Part3's coefficient, the
+ * exposure).  Each step does not decrease ll; the optimum over (mu, alpha)
+ * at fixed decays is its fixed point (there G_m = T_w and G_mn = C_mn
+ * wherever the bound is not active).  lr, history and adam_* are not used.
+ *
  * check_params: non-zero makes mdhp_fit_batch validate the initial values
  * first (mu > 0, alpha >= 0, beta > 0, all finite: the domain of Eq. (2)
  * and Eq. (5)) and return MDHP_E_PARAM without fitting if any window
@@ -135,7 +152,7 @@ typedef struct mdhp_batch {
  * finite ends as MDHP_FIT_NONFINITE. */
 typedef struct mdhp_fit_opts {
   int32_t max_steps; /* >= 0 */
-  int32_t optimizer; /* MDHP_OPT_PGD, MDHP_OPT_PADAM or MDHP_OPT_LBFGS */
+  int32_t optimizer; /* MDHP_OPT_PGD, MDHP_OPT_PADAM, MDHP_OPT_LBFGS or MDHP_OPT_EM */
   int32_t fix_beta;  /* non-zero: beta is not updated */
   int32_t history;   /* L-BFGS memory, 0 (= 8) .. MDHP_MAX_HISTORY */
   double lr;         /* > 0 (PGD, PADAM) */

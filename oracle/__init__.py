@@ -161,7 +161,7 @@ def scales(offsets, t, dim, T, M, mu, alpha, beta, beta_mode=0, nthreads=0):
 class FitOpts:
     """Projected gradient fit options (field order matches the C struct)."""
     max_steps: int = 500
-    optimizer: int = 1  # 0 projected gradient step, 1 projected Adam step, 2 projected L-BFGS
+    optimizer: int = 1  # 0 projected gradient step, 1 projected Adam step, 2 projected L-BFGS, 3 EM
     fix_beta: int = 0
     history: int = 8
     lr: float = 1e-2

@@ -27,7 +27,9 @@
 //                Adam step), projection mu >= mu_min, alpha >= 0,
 //                beta >= beta_min; the paper uses "a PyTorch optimizer" on
 //                -ll without naming it (Sec. IV-B), so the update rule is a
-//                stated reading, not the paper's.
+//                stated reading, not the paper's; projected L-BFGS; and EM on
+//                the branching structure with the decays fixed (the paper
+//                names EM among the estimators of related work).
 //
 // Layouts (host memory, caller-owned):
 //   offsets int64[W+1]; window w owns events [offsets[w], offsets[w+1])
@@ -422,12 +424,30 @@ int eval_batch(const int64_t* offsets, const double* t, const int32_t* dim,
   return 0;
 }
 
+// Part3's coefficient of alpha_mn (Appendix B), the exposure of dimension m
+// to the events of dimension n: C_mn = sum_{k: d_k = n} (1 - e^{-beta_mn
+// (T - t_k)}) / beta_mn, straight from its definition.
+std::vector<double> exposure(const Window& win, const Params& p) {
+  const int M = p.M;
+  std::vector<double> C((size_t)M * M, 0.0);
+  for (int64_t k = 0; k < win.n; ++k) {
+    const int n = win.d[k];
+    const double tau = win.T - win.t[k];
+    for (int m = 0; m < M; ++m) {
+      const double b = p.beta[(size_t)m * M + n];
+      C[(size_t)m * M + n] += -std::expm1(-b * tau) / b;
+    }
+  }
+  return C;
+}
+
 // Options of the projected gradient fit; same field order as the library's
 // public struct so that one Python packing serves both (declared separately:
 // the two share no source).
 struct FitOpts {
   int32_t max_steps;
-  int32_t optimizer;  // 0 projected gradient step, 1 projected Adam step, 2 projected L-BFGS
+  int32_t optimizer;  // 0 projected gradient step, 1 projected Adam step, 2 projected L-BFGS,
+                      // 3 EM (decays fixed)
   int32_t fix_beta;
   int32_t history;    // L-BFGS memory (0: 8)
   double lr;
@@ -629,7 +649,9 @@ int mdhp_oracle_fit(const int64_t* offsets, const double* t, const int32_t* dim,
   if (!opts_ptr || !mu || !alpha || !beta || !ll || !steps || !status) return -1;
   FitOpts o;
   std::memcpy(&o, opts_ptr, sizeof(o));
-  if (o.max_steps < 0 || !(o.lr > 0.0) || o.optimizer < 0 || o.optimizer > 2) return -1;
+  if (o.max_steps < 0 || o.optimizer < 0 || o.optimizer > 3) return -1;
+  if (o.optimizer <= 1 && !(o.lr > 0.0)) return -1;
+  if (o.optimizer == 3 && !o.fix_beta) return -1;  // EM keeps the decays
   int rc = check_batch(offsets, t, dim, T, W, M);
   if (rc) return rc;
   for (int64_t w = 0; w < W; ++w) {
@@ -733,6 +755,20 @@ int mdhp_oracle_fit(const int64_t* offsets, const double* t, const int32_t* dim,
         break;
       }
       ll_prev = l;
+      if (o.optimizer == 3) {
+        // EM on the branching structure (decays fixed): mu_m takes the
+        // expected number of background events of dimension m over T,
+        // alpha_mn the expected number of dimension-m offspring of
+        // dimension-n events over their exposure C_mn.  With G_m =
+        // sum_{i: d_i = m} 1 / lambda_i and G_mn = sum_{i: d_i = m} R_mn(i) /
+        // lambda_i these counts are mu_m G_m and alpha_mn G_mn, and the
+        // gradient gives G_m = dll/dmu_m + T, G_mn = dll/dalpha_mn + C_mn.
+        const std::vector<double> C = exposure(win, p);
+        for (int m = 0; m < M; ++m) th[m] = std::max(th[m] * (gv[m] + win.T) / win.T, mu_min);
+        for (int i = 0; i < MM; ++i)
+          if (C[i] > 0.0) th[M + i] = th[M + i] * (gv[M + i] + C[i]) / C[i];
+        continue;
+      }
       const double bc1 = 1.0 - std::pow(o.adam_b1, (double)(s + 1));
       const double bc2 = 1.0 - std::pow(o.adam_b2, (double)(s + 1));
       for (int i = 0; i < P; ++i) {

@@ -468,9 +468,10 @@ mdhp_status mdhp_fit_batch(mdhp_plan* p, const mdhp_fit_opts* o, float* mu, floa
   if (p->W > 0 && (!mu || !alpha || !beta || !ll || !steps || !status))
     return fail(MDHP_E_INVAL, "fit_batch: null pointer");
   if (o->max_steps < 0 || !(o->ll_tol >= 0.0) ||
-      (o->optimizer != MDHP_OPT_LBFGS && (!(o->lr > 0.0) || !std::isfinite(o->lr))) ||
+      ((o->optimizer == MDHP_OPT_PGD || o->optimizer == MDHP_OPT_PADAM) &&
+       (!(o->lr > 0.0) || !std::isfinite(o->lr))) ||
       (o->optimizer != MDHP_OPT_PGD && o->optimizer != MDHP_OPT_PADAM &&
-       o->optimizer != MDHP_OPT_LBFGS) ||
+       o->optimizer != MDHP_OPT_LBFGS && o->optimizer != MDHP_OPT_EM) ||
       o->history < 0 || o->history > MDHP_MAX_HISTORY ||
       !(o->mu_floor_rel >= 0.0) || !(o->beta_floor_rel >= 0.0) ||
       (o->optimizer == MDHP_OPT_PADAM &&
@@ -479,6 +480,8 @@ mdhp_status mdhp_fit_batch(mdhp_plan* p, const mdhp_fit_opts* o, float* mu, floa
     return fail(MDHP_E_INVAL, "fit_batch: invalid options");
   if (o->optimizer == MDHP_OPT_LBFGS && p->beta_mode != MDHP_BETA_SHARED)
     return fail(MDHP_E_INVAL, "fit_batch: L-BFGS needs one decay per window");
+  if (o->optimizer == MDHP_OPT_EM && !o->fix_beta)
+    return fail(MDHP_E_INVAL, "fit_batch: EM holds the decays; set fix_beta");
   if (o->check_params && p->W > 0) {
     const mdhp_status st = mdhp_check_params(p, mu, alpha, beta, stream);
     if (st != MDHP_OK)

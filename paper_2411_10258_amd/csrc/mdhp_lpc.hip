@@ -886,6 +886,25 @@ __device__ __forceinline__ void fit_one(Team<MP, NW>& sh, const Events& ev, int6
     b2t *= o.b2;
     const double bc1 = 1.0 - b1t, bc2 = 1.0 - b2t;
     team_sync<NW>();
+    if (o.optimizer == MDHP_OPT_EM) {
+      // Expected background and offspring counts over their exposures
+      // (the decays are fixed: kind 3 does not occur).
+      constexpr int Q = Team<MP, NW>::Q, TT = Team<MP, NW>::T;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int kd = sl.kind(k);
+        const double x = (double)sl.get(sh, k);
+        if (kd == 1) {
+          const int e = t + k * TT, nn = e % MP;
+          const double C = sh.Cn[nn];
+          if (C > 0.0) sl.set(sh, k, (float)(x * (sh.gR64[(e / MP) * Q + nn] / C)));
+        } else if (kd == 2) {
+          sl.set(sh, k, (float)fmax(x * (sh.gR64[t * Q + MP] / Tw), mu_min));
+        }
+      }
+      team_colsum(sh, M);
+      continue;
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int kd = sl.kind(k);

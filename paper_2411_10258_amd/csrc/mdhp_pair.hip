@@ -618,6 +618,7 @@ __global__ __launch_bounds__(PairCfg<P>::THREADS) void pair_fit_kernel(
         break;
       }
       ll_prev = l;
+      const bool em = o.optimizer == MDHP_OPT_EM;
       b1t *= o.b1;
       b2t *= o.b2;
       const double bc1 = 1.0 - b1t, bc2 = 1.0 - b2t;
@@ -639,7 +640,11 @@ __global__ __launch_bounds__(PairCfg<P>::THREADS) void pair_fit_kernel(
         na[k] = 0.f;
         if (e < P * P) {
           const int m = e / P, nn = e % P;
-          if (m < M && nn < M) {
+          if (m < M && nn < M && em) {
+            // Expected offspring count over its exposure (ga = G_mn - C_mn).
+            const double a = (double)sh.alpha[m * Q + nn], Cmn = (double)own.C[k];
+            na[k] = Cmn > 0.0 ? (float)(a * ((ga[k] + Cmn) / Cmn)) : (float)a;
+          } else if (m < M && nn < M) {
             na[k] = (float)fmax((double)sh.alpha[m * Q + nn] + step(ga[k], m1a[k], m2a[k]), 0.0);
             if (!o.fix_beta)
               own.beta[k] = (float)fmax((double)own.beta[k] + step(gb[k], m1b[k], m2b[k]),
@@ -648,7 +653,9 @@ __global__ __launch_bounds__(PairCfg<P>::THREADS) void pair_fit_kernel(
         }
       }
       float nmu = 0.f;
-      if (tid < M) nmu = (float)fmax((double)sh.mu[tid] + step(sh.gmu[tid], m1mu, m2mu), mu_min);
+      if (tid < M)
+        nmu = em ? (float)fmax((double)sh.mu[tid] * ((sh.gmu[tid] + T) / T), mu_min)
+                 : (float)fmax((double)sh.mu[tid] + step(sh.gmu[tid], m1mu, m2mu), mu_min);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < OWN; ++k) {

@@ -749,35 +749,50 @@ __global__ __launch_bounds__(kBlock, (P >= 32 ? 2 : kMinBlocks)) void shared_fit
         break;
       }
       ll_prev = l;
-      b1t *= o.b1;
-      b2t *= o.b2;
-      const double bc1 = 1.0 - b1t, bc2 = 1.0 - b2t;
-      auto step = [&](double g, float& m1, float& m2) -> double {
-        const double gn = g * inv_n;
-        if (o.optimizer == MDHP_OPT_PGD) return o.lr * gn;
-        const double nm1 = o.b1 * (double)m1 + (1.0 - o.b1) * gn;
-        const double nm2 = o.b2 * (double)m2 + (1.0 - o.b2) * gn * gn;
-        m1 = (float)nm1;
-        m2 = (float)nm2;
-        return o.lr * (nm1 / bc1) / (sqrt(nm2 / bc2) + o.eps);
-      };
+      if (o.optimizer == MDHP_OPT_EM) {
+        // Expected background and offspring counts over their exposures
+        // (the decay is fixed).
 #pragma unroll
-      for (int k = 0; k < OWN; ++k) {
-        const int e = tid + k * kBlock;
-        const int m = e / P, nn = e % P;
-        if (e < P * P && m < M && nn < M) {
-          const double g = gR64[k] - sh.Cn[nn];
-          const double v = (double)sh.A(e) + step(g, m1a[k], m2a[k]);
-          sh.A(e) = (float)fmax(v, 0.0);
+        for (int k = 0; k < OWN; ++k) {
+          const int e = tid + k * kBlock;
+          const int m = e / P, nn = e % P;
+          const double C = sh.Cn[nn];
+          if (e < P * P && m < M && nn < M && C > 0.0)
+            sh.A(e) = (float)((double)sh.A(e) * (gR64[k] / C));
         }
-      }
-      if (tid < M) {
-        const double v = (double)sh.mu[tid] + step(sh.gmu[tid], m1mu, m2mu);
-        sh.mu[tid] = (float)fmax(v, mu_min);
-      }
-      if (tid == 0 && !o.fix_beta) {
-        const double v = (double)sh.beta + step(sh.scal[1], m1b, m2b);
-        sh.beta = (float)fmax(v, beta_min);
+        if (tid < M)
+          sh.mu[tid] = (float)fmax((double)sh.mu[tid] * ((sh.gmu[tid] + T) / T), mu_min);
+      } else {
+        b1t *= o.b1;
+        b2t *= o.b2;
+        const double bc1 = 1.0 - b1t, bc2 = 1.0 - b2t;
+        auto step = [&](double g, float& m1, float& m2) -> double {
+          const double gn = g * inv_n;
+          if (o.optimizer == MDHP_OPT_PGD) return o.lr * gn;
+          const double nm1 = o.b1 * (double)m1 + (1.0 - o.b1) * gn;
+          const double nm2 = o.b2 * (double)m2 + (1.0 - o.b2) * gn * gn;
+          m1 = (float)nm1;
+          m2 = (float)nm2;
+          return o.lr * (nm1 / bc1) / (sqrt(nm2 / bc2) + o.eps);
+        };
+#pragma unroll
+        for (int k = 0; k < OWN; ++k) {
+          const int e = tid + k * kBlock;
+          const int m = e / P, nn = e % P;
+          if (e < P * P && m < M && nn < M) {
+            const double g = gR64[k] - sh.Cn[nn];
+            const double v = (double)sh.A(e) + step(g, m1a[k], m2a[k]);
+            sh.A(e) = (float)fmax(v, 0.0);
+          }
+        }
+        if (tid < M) {
+          const double v = (double)sh.mu[tid] + step(sh.gmu[tid], m1mu, m2mu);
+          sh.mu[tid] = (float)fmax(v, mu_min);
+        }
+        if (tid == 0 && !o.fix_beta) {
+          const double v = (double)sh.beta + step(sh.scal[1], m1b, m2b);
+          sh.beta = (float)fmax(v, beta_min);
+        }
       }
       __syncthreads();
       if (tid < P) {
