@@ -264,12 +264,16 @@ mdhp_status mdhp_check_params(mdhp_plan* plan, const float* mu, const float* alp
  *     layout in the plan depends on it; default 1024);
  *   kind 2 (one decay per window, 16 < M <= 64): the events per
  *     reduce-scatter of the intensity sums (4, 8 or 16 for M > 32; 4 or 8
- *     for M <= 32; default 8);
+ *     for M <= 32; default 8), or for M > 32 MDHP_SCATTER_MFMA: the
+ *     alpha contraction of Eq. (2) for blocks of 16 events as one product
+ *     R (16 x 64) alpha^T (64 x 64) on the matrix cores (FP32 MFMA), of
+ *     which each event keeps its own target's entry;
  *   kind 0 (per-pair decays): nothing to choose.
  * The schedule changes the order of floating-point sums, never the result
  * beyond rounding. */
 #define MDHP_TUNE_MAX 8
 #define MDHP_TEAM_NEVER 2147483647
+#define MDHP_SCATTER_MFMA 1
 
 typedef struct mdhp_tune_result {
   int32_t kind;                 /* 0, 1 or 2 as above */

@@ -32,6 +32,7 @@ STATUS_NAMES = {0: "MDHP_OK", -1: "MDHP_E_INVAL", -2: "MDHP_E_UNSORTED", -3: "MD
                 -4: "MDHP_E_PARAM", -5: "MDHP_E_NOMEM", -6: "MDHP_E_HIP", -7: "MDHP_E_IO"}
 BETA_SHARED, BETA_PAIR = 0, 1
 OPT_PGD, OPT_PADAM, OPT_LBFGS, OPT_EM = 0, 1, 2, 3
+SCATTER_MFMA = 1  # the M > 32 schedule with the intensity sums on the matrix cores
 FIT_CONVERGED, FIT_MAX_STEPS, FIT_NONFINITE, FIT_STALLED = 0, 1, 2, 3
 MAX_M = 64
 TUNE_MAX = 8

@@ -14,12 +14,12 @@ import torch
 
 from . import _lib
 from ._lib import (BETA_PAIR, BETA_SHARED, FIT_CONVERGED, FIT_MAX_STEPS, FIT_NONFINITE,
-                   FIT_STALLED, OPT_EM, OPT_LBFGS, OPT_PADAM, OPT_PGD, MdhpError)
+                   FIT_STALLED, OPT_EM, OPT_LBFGS, OPT_PADAM, OPT_PGD, SCATTER_MFMA, MdhpError)
 
 __all__ = ["Plan", "FitOptions", "mdhp_plan_create", "mdhp_plan_destroy", "mdhp_loglik",
            "mdhp_grad", "mdhp_fit_batch", "mdhp_check_params", "mdhp_cold_start", "mdhp_status_string",
            "mdhp_plan_autotune", "mdhp_plan_set_schedule", "mdhp_plan_schedule", "mdhp_grad_static",
-           "BETA_SHARED", "BETA_PAIR", "OPT_PGD", "OPT_PADAM", "OPT_LBFGS", "OPT_EM", "FIT_CONVERGED",
+           "BETA_SHARED", "BETA_PAIR", "OPT_PGD", "OPT_PADAM", "OPT_LBFGS", "OPT_EM", "SCATTER_MFMA", "FIT_CONVERGED",
            "FIT_MAX_STEPS", "FIT_NONFINITE", "FIT_STALLED", "MdhpError"]
 
 

@@ -589,7 +589,7 @@ int tune_candidates(const mdhp_plan* p, int32_t* kind, int32_t (&v)[MDHP_TUNE_MA
   }
   *kind = 2;
   int n = 0;
-  for (int32_t b : {4, 8, 16})
+  for (int32_t b : {4, 8, 16, (int32_t)MDHP_SCATTER_MFMA})
     if (shared_scatter_ok(p->M, b)) v[n++] = b;
   return n;
 }

@@ -142,6 +142,9 @@ constexpr int64_t kBigWindow = 1024;
 constexpr int kLpcBlock = 64 * MDHP_LPC_WAVES;
 // Default events per reduce-scatter of the M > 16 kernels.
 constexpr int kDefaultScatter = 8;
+// The scatter value of the M > 32 schedule that sums the intensities of
+// 16-event blocks on the matrix cores instead of a reduce-scatter.
+constexpr int kScatterMfma = MDHP_SCATTER_MFMA;
 __host__ __device__ inline int64_t lane_team(int64_t n, int64_t big_min) {
   return n >= big_min ? kLpcBlock : 64;
 }

@@ -59,6 +59,7 @@ constexpr int kBatch = MDHP_BATCH;
 constexpr int kScatter = kDefaultScatter;
 
 typedef float f32x32 __attribute__((ext_vector_type(32)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int P>
 struct SharedLds {
@@ -350,7 +351,11 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
     // the recursion with broadcast reads of the staged values, one
     // reduce-scatter for their intensities, log and reciprocal there, and
     // the G_R row adds.
-    constexpr int B = SB;
+    // SB = kScatterMfma: 16-event blocks whose intensity sums come from the
+    // matrix cores (P = 64 only).
+    constexpr bool kMfma = SB == kScatterMfma;
+    static_assert(!kMfma || P == 64, "the matrix-core intensity tile is built for 64 lanes");
+    constexpr int B = kMfma ? 16 : SB;
     constexpr int SH = P == 64 ? (B == 16 ? 2 : B == 8 ? 3 : 4) : (B == 16 ? 1 : B == 8 ? 2 : 3);
     const int ev_l = lane >> SH;                 // the event whose intensity this lane gets
     const bool lead = (lane & ((1 << SH) - 1)) == 0;
@@ -405,7 +410,47 @@ __device__ __forceinline__ void eval_window(SharedLds<P>& sh, const float* __res
         };
         if (ASM_GR && tie_free) recur(std::true_type{});
         else recur(std::false_type{});
-        float lam = group_reduce_scatter<P, B>(L);
+        float lam;
+        if constexpr (kMfma) {
+          // Lam[j][m] = sum_n R_n(j) alpha_mn for the block's 16 events and
+          // all 64 targets (one column per event is used): R staged in the
+          // wave's part of the G_R transfer buffer (free until the end of
+          // the window; rows padded to 65 floats), 16 steps of 4 sources x
+          // 4 tiles of 16 targets on v_mfma_f32_16x16x4_f32 (A: event
+          // lane % 16, source lane / 16; B: source lane / 16, target
+          // lane % 16; D: lane holds events 4 (lane / 16) + r, target
+          // lane % 16), then each event's own target read back.
+          constexpr int RS = P + 1;
+          float* Rt = sh.gR[0] + (tid >> 6) * (16 * RS);
+          static_for<B>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            Rt[j * RS + lane] = Rj[j];
+          });
+          wave_sync();
+          const int i16 = lane & 15, k4 = lane >> 4;
+          f32x4 acc[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int s4 = 0; s4 < P / 4; ++s4) {
+            const float a = Rt[i16 * RS + 4 * s4 + k4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                  a, sh.ao[(16 * q + i16) * P + 4 * s4 + k4].x, acc[q], 0, 0, 0);
+          }
+          wave_sync();  // every lane has read its A operands
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Rt[(4 * k4 + r) * RS + 16 * q + i16] = acc[q][r];
+          wave_sync();
+          const int dj = __builtin_bit_cast(int, meta[sb + ev_l].z);
+          lam = dj < P ? Rt[ev_l * RS + dj] : 0.f;
+          wave_sync();  // read before the next block's R overwrites the tile
+        } else {
+          lam = group_reduce_scatter<P, B>(L);
+        }
         const float4 me = meta[sb + ev_l];
         const bool valid = me.w >= 0.f;
         lam += me.w;
@@ -1181,6 +1226,8 @@ auto with_shape(int M, int scatter, F&& f) {
     default:
       if (scatter == 4) return f(integral_constant<int, 64>{}, integral_constant<int, 4>{});
       if (scatter == 16) return f(integral_constant<int, 64>{}, integral_constant<int, 16>{});
+      if (scatter == kScatterMfma)
+        return f(integral_constant<int, 64>{}, integral_constant<int, kScatterMfma>{});
       return f(integral_constant<int, 64>{}, integral_constant<int, 8>{});
   }
 }
@@ -1227,7 +1274,7 @@ int64_t shared_lbfgs_workspace(int M, int64_t W) {
 
 bool shared_scatter_ok(int M, int scatter) {
   const int p = lanes_for(M);
-  if (p == 64) return scatter == 4 || scatter == 8 || scatter == 16;
+  if (p == 64) return scatter == 4 || scatter == 8 || scatter == 16 || scatter == kScatterMfma;
   if (p == 32) return scatter == 4 || scatter == 8;
   return scatter == kScatter;
 }

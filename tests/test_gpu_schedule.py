@@ -46,7 +46,8 @@ def _check(gpu, oracle, plan, b, th, label):
 @pytest.mark.parametrize("M,values,tie_grid", [
     (16, [512, 1024, 2048, 4096, 2147483647], 0.0),
     (5, [512, 2048, 2147483647], 0.5),
-    (64, [4, 8, 16], 0.0),
+    (64, [4, 8, 16, 1], 0.0),   # 1: intensity sums of 16-event blocks on the matrix cores
+    (40, [1, 8], 0.25),
     (33, [4, 8], 0.25),
 ])
 def test_every_schedule_matches_oracle(gpu, oracle_lib, synth_lib, M, values, tie_grid):
@@ -109,4 +110,32 @@ def test_autotune_keeps_fastest(gpu, oracle_lib, synth_lib, M, fit):
     l_or = oracle_lib.loglik(*args)
     ls = oracle_lib.scales(*args)[0]
     assert ll_errors(ll[sub], l_or, ls).max() <= LL_TOL
+    plan.close()
+
+
+def test_mfma_schedule_fits_match_oracle(gpu, oracle_lib, synth_lib):
+    """The matrix-core intensity schedule inside the fit kernels, with many
+    windows per workgroup: the reported ll is the oracle's ll at the
+    returned parameters, and fixed-update fits track the oracle's."""
+    import torch
+    b = synth_lib.random_small(711, 1024, 64, 0, n_lo=60, n_hi=700, nthreads=16)
+    last = np.argsort(b.counts, kind="stable")[:24]
+    s = b.subset(last)
+    plan = gpu.Plan(b.offsets, b.t, b.dim, b.T, 64, 0, schedule=gpu.SCATTER_MFMA)
+    assert plan.schedule == gpu.SCATTER_MFMA
+    x0 = plan.cold_start()
+    x0_host = tuple(x.cpu().numpy() for x in x0)
+    for rule, kw in (("lbfgs", dict(max_steps=12, optimizer=2, ll_tol=0.0, history=5)),
+                     ("pgd", dict(max_steps=15, optimizer=0, ll_tol=0.0, lr=0.1))):
+        print(f"[schedule] M=64 matrix-core intensities, {rule} fit", flush=True)
+        mu, al, be, llf, st, stat = (x.cpu().numpy() for x in plan.fit(
+            *(x.clone() for x in x0), gpu.FitOptions(**kw)))
+        fargs = (b.offsets, b.t, b.dim, b.T, 64, mu, al, be, 0)
+        l_at = oracle_lib.loglik(*fargs, nthreads=16)
+        e = ll_errors(llf, l_at, oracle_lib.scales(*fargs, nthreads=16)[0])
+        assert e.max() <= LL_TOL, f"{rule}: window {e.argmax()}"
+        r = oracle_lib.fit(s.offsets, s.t, s.dim, s.T, 64, *(x[last] for x in x0_host),
+                           oracle_lib.FitOpts(**kw), nthreads=16)
+        ls_or = oracle_lib.scales(s.offsets, s.t, s.dim, s.T, 64, r[0], r[1], r[2], 0)[0]
+        assert ll_errors(l_at[last], r[3], ls_or).max() <= 1e-4
     plan.close()
