@@ -409,6 +409,83 @@ mdhp_status mdhp_warm_start(mdhp_plan* plan, const float* pred, const float* mea
                             const float* alpha_cold, const float* beta_cold, float* mu,
                             float* alpha, float* beta, int32_t* used_warm, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Simulation of MDHP windows on the device: Ogata's thinning for the model of
+ * Eq. (2) with one decay per window (M <= 64) or per pair
+ * (M <= MDHP_SIM_PAIR_MAX_M), one window per wavefront, FP64 throughout.
+ * The total intensity at the current time bounds it until the next event;
+ * a candidate s' = s + Exp(bound) is accepted with probability
+ * sum_m lambda_m(s') / bound and takes the first dimension whose cumulative
+ * intensity reaches a uniform fraction of the total.  Window w draws the
+ * SplitMix64 stream (seed, first_window + w) (Steele, Lea and Flood 2014;
+ * one word from a generator seeded with seed ^ 0x6A09E667F3BCC909, keyed with
+ * the window index), so a window does not depend on the batch it is
+ * simulated in.
+ *
+ * mode MDHP_SIM_UNTIL_T: window w runs on [0, T_in[w]] with room for
+ *   offsets[w+1] - offsets[w] events; n_out[w] = its events, T_out[w] =
+ *   T_in[w]; a window with more events than its room stops there with
+ *   n_out[w] = -1.
+ * mode MDHP_SIM_COUNT: window w gets exactly offsets[w+1] - offsets[w]
+ *   events (n_out[w]) and ends at the time of the next accepted one
+ *   (T_out[w]); T_in is not read.
+ * In either mode n_out[w] = -2 where the window cannot be drawn: a total
+ * intensity that is negative, infinite or NaN at some step, a zero one
+ * while MDHP_SIM_COUNT still owes events, or T_in[w] negative or not
+ * finite; the window's outputs are then undefined.
+ * Device memory, caller-owned: mu [W][M], alpha [W][M][M] (alpha[w][m][n]:
+ * source n excites target m), beta [W] or [W][M][M], T_in [W], offsets
+ * [W+1]; outputs t_out [offsets[W]] (event times), dim_out [offsets[W]],
+ * written from offsets[w] on, n_out [W], T_out [W].  Parameters are not
+ * validated beyond that check (mu > 0, alpha >= 0, beta > 0 and a stable
+ * branching matrix are the caller's; an unstable one fills the room).
+ * MDHP_E_INVAL for bad sizes or modes.  Enqueued on stream. */
+#define MDHP_SIM_UNTIL_T 0
+#define MDHP_SIM_COUNT 1
+#define MDHP_SIM_PAIR_MAX_M 32
+mdhp_status mdhp_simulate(int64_t W, int32_t M, int32_t beta_mode, const double* mu,
+                          const double* alpha, const double* beta, int32_t mode,
+                          const double* T_in, const int64_t* offsets, uint64_t seed,
+                          int64_t first_window, double* t_out, int32_t* dim_out, int64_t* n_out,
+                          double* T_out, void* stream);
+
+/* Injection times of the paper's time-exciting attack strategies (attack
+ * rates g(t) of Sec. III's strategy table) drawn by its three samplers
+ * (appendix, sampling algorithms), one attack window per GPU thread:
+ *   MDHP_ATTACK_PLA  g = a t^b                                  params (a, b)
+ *   MDHP_ATTACK_DEA  g = W1 a1 t^(a1 - 1) for t < t1, W2 a2 e^(c (t - t1)) after
+ *                                                  params (W1, a1, W2, a2, c, t1)
+ *   MDHP_ATTACK_ASA  g = C e^(c t) / (1 + e^(c (t - t0)))^2     params (C, c, t0)
+ *   MDHP_ATTACK_DAM  g = w a1 t^(a1 - 1) + (1 - w) a2 e^(a2 t)  params (w, a1, a2)
+ *   MDHP_SAMPLER_NPP candidates with Exp gaps of mean 1 / r, a candidate t
+ *     kept when a Uniform(0, g_max) draw is below g(t);
+ *   MDHP_SAMPLER_ND  candidates with gaps |Normal(1 / r, 1 / (2 r))|, kept
+ *     with probability g(t) / g_max;
+ *   MDHP_SAMPLER_DRP DAM (a1 = params[1], a2 = params[2]) whose weight w is
+ *     drawn per third of the range from U(0, 1/3), U(1/3, 2/3), U(2/3, 1),
+ *     then NPP's thinning (strategy[a] is not read).
+ * r = params[7] (512 when 0); g_max is the largest g on a grid of 4,097
+ * points of the range (the paper takes it from evaluations of g).  Attack a
+ * draws SplitMix64 stream (seed, first + a) as mdhp_simulate does.  Device
+ * memory, caller-owned: strategy [A], sampler [A], params [A][8], range
+ * [A][2] (t_min, t_max; the paper normalises windows to [0, 1]), offsets
+ * [A+1] (room per attack); outputs t_out (increasing times from offsets[a]
+ * on) and n_out [A]: -1 where the room was too small, -2 where the range
+ * is not one (t_max < t_min, NaN or infinite ends) or
+ * r (t_max - t_min) exceeds 2^24 candidates.  MDHP_E_INVAL for bad sizes;
+ * the rate parameters are the caller's.  Enqueued on stream. */
+#define MDHP_ATTACK_PLA 0
+#define MDHP_ATTACK_DEA 1
+#define MDHP_ATTACK_ASA 2
+#define MDHP_ATTACK_DAM 3
+#define MDHP_SAMPLER_NPP 0
+#define MDHP_SAMPLER_ND 1
+#define MDHP_SAMPLER_DRP 2
+mdhp_status mdhp_attack_times(int64_t A, const int32_t* strategy, const int32_t* sampler,
+                              const double* params, const double* range, const int64_t* offsets,
+                              uint64_t seed, int64_t first, double* t_out, int64_t* n_out,
+                              void* stream);
+
 /* Static description of a status code. */
 const char* mdhp_status_string(mdhp_status status);
 

@@ -24,7 +24,8 @@ EXPORTS = (
     "mdhp_surrogate_backward", "mdhp_surrogate_get_gradients", "mdhp_surrogate_adam",
     "mdhp_surrogate_train_step", "mdhp_warm_start", "mdhp_cold_start", "mdhp_plan_autotune",
     "mdhp_plan_set_schedule", "mdhp_plan_schedule", "mdhp_plan_create_scheduled",
-    "mdhp_surrogate_save", "mdhp_surrogate_load", "mdhp_grad_static",
+    "mdhp_surrogate_save", "mdhp_surrogate_load", "mdhp_grad_static", "mdhp_simulate",
+    "mdhp_attack_times",
 )
 
 MDHP_OK = 0
@@ -33,6 +34,9 @@ STATUS_NAMES = {0: "MDHP_OK", -1: "MDHP_E_INVAL", -2: "MDHP_E_UNSORTED", -3: "MD
 BETA_SHARED, BETA_PAIR = 0, 1
 OPT_PGD, OPT_PADAM, OPT_LBFGS, OPT_EM = 0, 1, 2, 3
 SCATTER_MFMA = 1  # the M > 32 schedule with the intensity sums on the matrix cores
+SIM_UNTIL_T, SIM_COUNT = 0, 1
+ATTACK_PLA, ATTACK_DEA, ATTACK_ASA, ATTACK_DAM = 0, 1, 2, 3
+SAMPLER_NPP, SAMPLER_ND, SAMPLER_DRP = 0, 1, 2
 FIT_CONVERGED, FIT_MAX_STEPS, FIT_NONFINITE, FIT_STALLED = 0, 1, 2, 3
 MAX_M = 64
 TUNE_MAX = 8
@@ -120,6 +124,9 @@ def load() -> ctypes.CDLL:
     lib.mdhp_surrogate_save.argtypes = [P, ctypes.c_char_p, P, I64, P]
     lib.mdhp_surrogate_load.argtypes = [P, ctypes.c_char_p, P, I64, ctypes.POINTER(I64), P]
     lib.mdhp_grad_static.argtypes = [ctypes.POINTER(MdhpBatch), I32, P, P, P, P, P, P, P, P]
+    lib.mdhp_simulate.argtypes = [I64, I32, I32, P, P, P, I32, P, P, ctypes.c_uint64, I64, P, P,
+                                  P, P, P]
+    lib.mdhp_attack_times.argtypes = [I64, P, P, P, P, P, ctypes.c_uint64, I64, P, P, P]
     lib.mdhp_status_string.argtypes = [I32]
     lib.mdhp_status_string.restype = ctypes.c_char_p
     lib.mdhp_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
@@ -130,7 +137,8 @@ def load() -> ctypes.CDLL:
                  "mdhp_surrogate_get_hidden", "mdhp_surrogate_backward", "mdhp_surrogate_adam",
                  "mdhp_surrogate_train_step", "mdhp_warm_start", "mdhp_cold_start",
                  "mdhp_plan_autotune", "mdhp_plan_set_schedule", "mdhp_surrogate_save",
-                 "mdhp_surrogate_load", "mdhp_grad_static"):
+                 "mdhp_surrogate_load", "mdhp_grad_static", "mdhp_simulate",
+                 "mdhp_attack_times"):
         getattr(lib, name).restype = I32
     _lib = lib
     return lib

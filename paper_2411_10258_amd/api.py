@@ -19,6 +19,7 @@ from ._lib import (BETA_PAIR, BETA_SHARED, FIT_CONVERGED, FIT_MAX_STEPS, FIT_NON
 __all__ = ["Plan", "FitOptions", "mdhp_plan_create", "mdhp_plan_destroy", "mdhp_loglik",
            "mdhp_grad", "mdhp_fit_batch", "mdhp_check_params", "mdhp_cold_start", "mdhp_status_string",
            "mdhp_plan_autotune", "mdhp_plan_set_schedule", "mdhp_plan_schedule", "mdhp_grad_static",
+           "mdhp_simulate", "mdhp_attack_times",
            "BETA_SHARED", "BETA_PAIR", "OPT_PGD", "OPT_PADAM", "OPT_LBFGS", "OPT_EM", "SCATTER_MFMA", "FIT_CONVERGED",
            "FIT_MAX_STEPS", "FIT_NONFINITE", "FIT_STALLED", "MdhpError"]
 
@@ -124,6 +125,91 @@ def mdhp_grad_static(batch, M: int, mu, alpha, beta, ll, g_mu=None, g_alpha=None
     _lib.check(_lib.load().mdhp_grad_static(
         ctypes.byref(b), int(M), _ptr(mu), _ptr(alpha), _ptr(beta), _ptr(ll),
         *(None if g is None else _ptr(g) for g in grads), ctypes.c_void_p(_stream(stream))))
+
+
+def mdhp_simulate(mu, alpha, beta, *, counts=None, T_end=None, cap=None, seed: int = 2024,
+                  first_window: int = 0, device="cuda", stream=None):
+    """Ogata thinning on the device for W windows (mdhp_simulate).
+
+    mu [W, M], alpha [W, M, M], beta [W] (one decay per window) or [W, M, M]
+    (per pair); host arrays or device tensors, used in FP64.  Exactly one of
+    ``counts`` (int[W]: exactly counts[w] events, the window ending at the
+    next accepted one) or ``T_end`` (float[W]: events on [0, T_end[w]], at
+    most ``cap[w]``) must be given.  Returns device tensors (offsets int64[W+1],
+    t float64, dim int32, T float64[W]) in the batch layout of Plan."""
+    dev = torch.device(device)
+    f64 = dict(dtype=torch.float64, device=dev)
+    mu, alpha, beta = (torch.as_tensor(x).to(**f64).contiguous() for x in (mu, alpha, beta))
+    W, M = mu.shape
+    beta_mode = BETA_SHARED if beta.dim() == 1 else BETA_PAIR
+    if (counts is None) == (T_end is None):
+        raise ValueError("give exactly one of counts and T_end")
+    if counts is not None:
+        mode, room = _lib.SIM_COUNT, torch.as_tensor(counts, dtype=torch.int64)
+        T_in = None
+    else:
+        mode, room = _lib.SIM_UNTIL_T, torch.as_tensor(cap, dtype=torch.int64)
+        T_in = torch.as_tensor(T_end).to(**f64).contiguous()
+    off = torch.zeros(W + 1, dtype=torch.int64)
+    torch.cumsum(room.cpu(), 0, out=off[1:])
+    total = int(off[-1])
+    off = off.to(dev)
+    t = torch.zeros(total, **f64)
+    dim = torch.zeros(total, dtype=torch.int32, device=dev)
+    n_out = torch.zeros(W, dtype=torch.int64, device=dev)
+    T_out = torch.zeros(W, **f64)
+    _lib.check(_lib.load().mdhp_simulate(
+        W, M, beta_mode, _ptr(mu), _ptr(alpha), _ptr(beta), mode,
+        _ptr(T_in) if T_in is not None else None, _ptr(off), ctypes.c_uint64(seed),
+        int(first_window), _ptr(t), _ptr(dim), _ptr(n_out), _ptr(T_out),
+        ctypes.c_void_p(_stream(stream))))
+    n = n_out.cpu()
+    if bool((n == -2).any()):
+        raise MdhpError(-1, "simulate: a window's intensity is not finite and positive "
+                            "(parameters) or its T_end is not finite")
+    if bool((n < 0).any()):
+        raise MdhpError(-1, "simulate: a window has more events than its room (cap)")
+    if mode == _lib.SIM_COUNT:
+        return off, t, dim, T_out
+    keep = torch.cat([torch.arange(int(off[w]), int(off[w]) + int(n[w])) for w in range(W)]) \
+        if W else torch.zeros(0, dtype=torch.int64)
+    keep = keep.to(dev)
+    off_c = torch.zeros(W + 1, dtype=torch.int64)
+    torch.cumsum(n, 0, out=off_c[1:])
+    return off_c.to(dev), t[keep], dim[keep], T_out
+
+
+def mdhp_attack_times(strategy, sampler, params, t_range, cap, *, seed: int = 2024,
+                      first: int = 0, device="cuda", stream=None):
+    """Injection times of A attack windows (mdhp_attack_times): strategy and
+    sampler int[A], params float[A, 8], t_range float[A, 2], cap int[A] (room
+    per attack).  Returns device tensors (offsets int64[A+1], t float64)."""
+    dev = torch.device(device)
+    st = torch.as_tensor(strategy, dtype=torch.int32).to(dev).contiguous()
+    sm = torch.as_tensor(sampler, dtype=torch.int32).to(dev).contiguous()
+    p = torch.as_tensor(params, dtype=torch.float64).to(dev).contiguous()
+    rg = torch.as_tensor(t_range, dtype=torch.float64).to(dev).contiguous()
+    A = st.numel()
+    room = torch.as_tensor(cap, dtype=torch.int64).cpu()
+    off = torch.zeros(A + 1, dtype=torch.int64)
+    torch.cumsum(room, 0, out=off[1:])
+    t = torch.zeros(int(off[-1]), dtype=torch.float64, device=dev)
+    n_out = torch.zeros(A, dtype=torch.int64, device=dev)
+    off_d = off.to(dev)
+    _lib.check(_lib.load().mdhp_attack_times(
+        A, _ptr(st), _ptr(sm), _ptr(p), _ptr(rg), _ptr(off_d), ctypes.c_uint64(seed), int(first),
+        _ptr(t), _ptr(n_out), ctypes.c_void_p(_stream(stream))))
+    n = n_out.cpu()
+    if bool((n == -2).any()):
+        raise MdhpError(-1, "attack_times: a range is not finite and ordered, or needs more "
+                            "than 2^24 candidates")
+    if bool((n < 0).any()):
+        raise MdhpError(-1, "attack_times: an attack has more injections than its room (cap)")
+    keep = torch.cat([torch.arange(int(off[a]), int(off[a]) + int(n[a])) for a in range(A)]) \
+        if A else torch.zeros(0, dtype=torch.int64)
+    off_c = torch.zeros(A + 1, dtype=torch.int64)
+    torch.cumsum(n, 0, out=off_c[1:])
+    return off_c.to(dev), t[keep.to(dev)]
 
 
 def mdhp_fit_batch(handle, opts: FitOptions, mu, alpha, beta, ll, steps, status, evals=None,

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdhp.so")
-SOURCES = ["mdhp_api.hip", "mdhp_lpc.hip", "mdhp_shared.hip", "mdhp_pair.hip", "mdhp_surrogate.hip"]
+SOURCES = ["mdhp_api.hip", "mdhp_lpc.hip", "mdhp_shared.hip", "mdhp_pair.hip", "mdhp_surrogate.hip",
+           "mdhp_sim.hip"]
 ARCH = os.environ.get("MDHP_OFFLOAD_ARCH", "gfx950")
 
 
