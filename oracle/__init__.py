@@ -15,6 +15,8 @@ Appendices A and B):
 * ``brute.py``: a second, pure-Python brute force of Eq. (5) for tiny inputs.
 * ``quadrature.py``: the integral Gamma of Eq. (4) by numerical quadrature,
   which checks the closed form of Appendix B independently.
+* ``lstm.py``: the MDHP-LSTM layer of Eq. (7), forward and its gradient,
+  in FP64 numpy.
 """
 
 from __future__ import annotations
