@@ -486,6 +486,56 @@ mdhp_status mdhp_attack_times(int64_t A, const int32_t* strategy, const int32_t*
                               uint64_t seed, int64_t first, double* t_out, int64_t* n_out,
                               void* stream);
 
+/* ------------------------------------------------------------------------
+ * The MDHP-LSTM layer (Sec. IV, "MDHP-LSTM", Eq. (7)), FP32, forward and
+ * backward.  For B sequences of L inputs x_t (width D), hidden width H and
+ * each sequence's fitted window parameters (alpha, beta, theta = mu) and
+ * length T_span:
+ *   hks = tanh(A vec(alpha) - B (beta T_span) + C theta)      once per sequence
+ *   z_t = W x_t + U h_{t-1} + b;  i, f, o = sigmoid, g = tanh of its blocks
+ *   c_t = hks * (f c_{t-1} + i g);  h_t = o tanh(c_t);  h_{-1} = c_{-1} = 0.
+ * hks carries only window quantities, so it is computed once and gates
+ * every step; the paper's readout y = W_y h is a plain linear layer left to
+ * the caller.  Gate blocks are ordered i, f, g, o (torch.nn.LSTM's order).
+ * Layouts (row-major, device memory, caller-owned): x [B][L][D], W [4H][D],
+ * U [4H][H], bias [4H], Whks [H][Kf] = [A | B | C] with Kf = M^2 + Kb + M
+ * (Kb = 1 for one decay per window, M^2 for one per pair), alpha [B][M][M],
+ * beta [B] or [B][M][M], T_span [B], theta [B][M]; h [B][L][H] out.
+ * `saved` (mdhp_lstm_sizes' first count of floats) receives what the
+ * backward pass reads: gate activations [B][L][4H], cells [B][L][H], hks
+ * [B][H] and the features [B][Kf]; `work` (its second count) is scratch.
+ * H must be 64, 128 or 256; MDHP_E_INVAL for bad sizes or null pointers.
+ * Enqueued on stream. */
+typedef struct mdhp_lstm_dims {
+  int32_t B;         /* sequences */
+  int32_t L;         /* steps per sequence, >= 1 */
+  int32_t D;         /* input width, >= 1 */
+  int32_t H;         /* hidden width: 64, 128 or 256 */
+  int32_t M;         /* MDHP dimensions, 1..64 */
+  int32_t beta_mode; /* MDHP_BETA_SHARED or MDHP_BETA_PAIR */
+} mdhp_lstm_dims;
+
+/* Floats of the saved state and of the workspace for these dimensions. */
+mdhp_status mdhp_lstm_sizes(const mdhp_lstm_dims* dims, int64_t* saved_floats,
+                            int64_t* work_floats);
+mdhp_status mdhp_lstm_forward(const mdhp_lstm_dims* dims, const float* x, const float* W,
+                              const float* U, const float* bias, const float* Whks,
+                              const float* alpha, const float* beta, const float* T_span,
+                              const float* theta, float* h, float* saved, float* work,
+                              void* stream);
+/* Gradients of a loss whose gradient with respect to every output h_t is
+ * dh [B][L][H]: dx [B][L][D], dW [4H][D], dU [4H][H], dbias [4H], dWhks
+ * [H][Kf] (= [dA | dB | dC]) and dfeat [B][Kf] (with respect to vec(alpha),
+ * beta T_span and theta).  x, W, U, Whks and h are the forward pass's;
+ * `saved` is the forward pass's and is consumed (its gate activations are
+ * overwritten by the gradients of their pre-activations).  Outputs are
+ * overwritten, not accumulated.  With B = 0 the arrays of B rows may be
+ * null and the weight gradients come out zero. */
+mdhp_status mdhp_lstm_backward(const mdhp_lstm_dims* dims, const float* x, const float* W,
+                               const float* U, const float* Whks, const float* h, float* saved,
+                               const float* dh, float* dx, float* dW, float* dU, float* dbias,
+                               float* dWhks, float* dfeat, float* work, void* stream);
+
 /* Static description of a status code. */
 const char* mdhp_status_string(mdhp_status status);
 

@@ -25,7 +25,7 @@ EXPORTS = (
     "mdhp_surrogate_train_step", "mdhp_warm_start", "mdhp_cold_start", "mdhp_plan_autotune",
     "mdhp_plan_set_schedule", "mdhp_plan_schedule", "mdhp_plan_create_scheduled",
     "mdhp_surrogate_save", "mdhp_surrogate_load", "mdhp_grad_static", "mdhp_simulate",
-    "mdhp_attack_times",
+    "mdhp_attack_times", "mdhp_lstm_sizes", "mdhp_lstm_forward", "mdhp_lstm_backward",
 )
 
 MDHP_OK = 0
@@ -57,6 +57,11 @@ class MdhpFitOpts(ctypes.Structure):
                 ("adam_b1", ctypes.c_double), ("adam_b2", ctypes.c_double),
                 ("adam_eps", ctypes.c_double), ("check_params", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+class MdhpLstmDims(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_int32), ("L", ctypes.c_int32), ("D", ctypes.c_int32),
+                ("H", ctypes.c_int32), ("M", ctypes.c_int32), ("beta_mode", ctypes.c_int32)]
 
 
 class MdhpTuneResult(ctypes.Structure):
@@ -127,6 +132,10 @@ def load() -> ctypes.CDLL:
     lib.mdhp_simulate.argtypes = [I64, I32, I32, P, P, P, I32, P, P, ctypes.c_uint64, I64, P, P,
                                   P, P, P]
     lib.mdhp_attack_times.argtypes = [I64, P, P, P, P, P, ctypes.c_uint64, I64, P, P, P]
+    LD = ctypes.POINTER(MdhpLstmDims)
+    lib.mdhp_lstm_sizes.argtypes = [LD, ctypes.POINTER(I64), ctypes.POINTER(I64)]
+    lib.mdhp_lstm_forward.argtypes = [LD, P, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.mdhp_lstm_backward.argtypes = [LD, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.mdhp_status_string.argtypes = [I32]
     lib.mdhp_status_string.restype = ctypes.c_char_p
     lib.mdhp_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
@@ -138,7 +147,8 @@ def load() -> ctypes.CDLL:
                  "mdhp_surrogate_train_step", "mdhp_warm_start", "mdhp_cold_start",
                  "mdhp_plan_autotune", "mdhp_plan_set_schedule", "mdhp_surrogate_save",
                  "mdhp_surrogate_load", "mdhp_grad_static", "mdhp_simulate",
-                 "mdhp_attack_times"):
+                 "mdhp_attack_times", "mdhp_lstm_sizes", "mdhp_lstm_forward",
+                 "mdhp_lstm_backward"):
         getattr(lib, name).restype = I32
     _lib = lib
     return lib

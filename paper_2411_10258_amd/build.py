@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdhp.so")
 SOURCES = ["mdhp_api.hip", "mdhp_lpc.hip", "mdhp_shared.hip", "mdhp_pair.hip", "mdhp_surrogate.hip",
-           "mdhp_sim.hip"]
+           "mdhp_sim.hip", "mdhp_lstm.hip"]
 ARCH = os.environ.get("MDHP_OFFLOAD_ARCH", "gfx950")
 
 
