@@ -36,6 +36,11 @@ One timed step = the whole hot path over the batch, inputs resident in HBM:
          (BF16 MFMA) + mdhp_warm_start (likelihood passes, per-window
          fallback to the cold start) + mdhp_fit_batch.
 
+--workload mdhp_lstm times the MDHP-LSTM layer (Eq. (7)) instead: forward
+and backward of 4,096 sequences of 128 steps, D = H = 256, M = 16, per step
+(sequences per second), the dominant phase's roofline from the library's
+own HIP events, and the FP64 oracle on a sample of sequences.
+
 ``value`` is warm-start L-BFGS fits at tolerance per second (cold start with
 --no-warm).  The line also carries every run, the speed-ups, event
 evaluations per second, the fit kernel's roofline (HIP events on its stream)
@@ -221,6 +226,93 @@ def bench_pair(args, dev) -> int:
                                "sample": f"likelihood+gradient of the first 8 windows "
                                          f"({s.n_events} events), {reps} repetitions, {dt:.1f} s"}
     plan.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def lstm_flops(B, L, D, H, Kf) -> dict:
+    """Algorithmic FLOPs of each phase of one MDHP-LSTM forward and backward
+    pass (multiply-adds count two; the recurrences skip the first step's
+    h_{-1} U product, which is zero; the backward recurrence's bias sums and
+    the phases' elementwise work are not counted)."""
+    G = 4 * H
+    return {"fwd.hks_gemm": 2.0 * B * Kf * H, "fwd.input_gemm": 2.0 * B * L * D * G,
+            "fwd.recurrence": 2.0 * B * (L - 1) * H * G,
+            "bwd.recurrence": 2.0 * B * (L - 1) * G * H, "bwd.dx_gemm": 2.0 * B * L * G * D,
+            "bwd.dW_gemm": 2.0 * B * L * G * D, "bwd.dU_gemm": 2.0 * B * (L - 1) * G * H,
+            "bwd.hawkes_gate": 4.0 * B * H * Kf}
+
+
+def bench_lstm(args, dev) -> int:
+    """mdhp_lstm: one MDHP-LSTM layer forward + backward per step."""
+    import numpy as np
+    import torch
+
+    from synth import lstm_inputs
+    import paper_2411_10258_amd as mdhp
+
+    B = args.windows or 4096
+    L, D, H, M = 128, 256, 256, 16
+    c = lstm_inputs.case(2024, B, L, D, H, M)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    x, W, U, bias, Whks, al, be, T, th, dh = (t(a) for a in (
+        c.x, c.W, c.U, c.bias, c.Whks, c.alpha, c.beta, c.T_span, c.theta, c.dh))
+
+    def step():
+        h, saved, work = mdhp.mdhp_lstm_forward(x, W, U, bias, Whks, al, be, T, th)
+        g = mdhp.mdhp_lstm_backward(x, W, U, Whks, h, saved, work, dh, M, mdhp.BETA_SHARED)
+        return h, g
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    mdhp.mdhp_lstm_timing(True)
+    phases = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        f, b = mdhp.mdhp_lstm_phase_ms()
+        phases.append({**{"fwd." + k: v for k, v in f.items()},
+                       **{"bwd." + k: v for k, v in b.items()}})
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    mdhp.mdhp_lstm_timing(False)
+    avg = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
+    flops = lstm_flops(B, L, D, H, c.Whks.shape[1])
+    top = max(flops, key=lambda k: avg[k])
+    ach = flops[top] / (avg[top] * 1e-3) / 1e12
+    total_flops = sum(flops.values())
+    out = {
+        "metric": "MDHP-LSTM layer forward+backward sequences/s", "value": B / (ms * 1e-3),
+        "unit": "sequences/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded normal inputs, uniform weights and MDHP "
+                                "parameters, seed 2024)",
+        "config": {"workload": f"mdhp_lstm: {B} sequences x {L} steps, D={D}, H={H}, M={M}, "
+                               "one decay per window; forward + backward per step",
+                   "global_batch": B, "parallelism": "none (1 GPU)"},
+        "phase_ms": avg,
+        "step_tflops": total_flops / (ms * 1e-3) / 1e12,
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": top, "flops_per_launch": flops[top]},
+    }
+    if not args.no_cpu:
+        from oracle import lstm as olstm
+        A, Bm, C = c.split_whks()
+        n, reps, t0 = 0, 0, time.perf_counter()
+        while time.perf_counter() - t0 < 10.0:
+            rows = slice(16 * reps % B, 16 * reps % B + 16)
+            olstm.backward(c.x[rows], c.W, c.U, c.bias, A, Bm, C, c.alpha[rows], c.beta[rows],
+                           c.T_span[rows], c.theta[rows], c.dh[rows])
+            n += 16
+            reps += 1
+        dt = time.perf_counter() - t0
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = {"value": n / dt, "unit": "sequences/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"forward+backward of {n} sequences (16 at a time) of "
+                                         f"the same workload, {dt:.1f} s, numpy FP64"}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -484,13 +576,14 @@ def run_fit_workload(args, name: str, dev, log, cpu: bool) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["large_m64", "batch_m16", "pair_m32"],
+    ap.add_argument("--workload", choices=["large_m64", "batch_m16", "pair_m32", "mdhp_lstm"],
                     default="large_m64",
                     help="large_m64: warm vs cold fits of 16,384 M=64 windows (~151M events, "
                          "default; the M=16 batch follows as extra keys unless --no-m16); "
                          "batch_m16: warm vs cold fits of 4,096 M=16 windows; "
                          "pair_m32: likelihood+gradient passes over 1,024 x 5,000 events "
-                         "with per-pair decays")
+                         "with per-pair decays; mdhp_lstm: the MDHP-LSTM layer's forward and "
+                         "backward over 4,096 sequences of 128 steps")
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--windows", type=int, default=0, help="0: the workload's size")
@@ -545,6 +638,8 @@ def main() -> int:
         if not args.windows:
             args.windows = 1024
         return bench_pair(args, dev)
+    if args.workload == "mdhp_lstm":
+        return bench_lstm(args, dev)
     log = lambda m: print(m, file=sys.stderr, flush=True)
     r = run_fit_workload(args, args.workload, dev, log, cpu=not args.no_cpu)
     out = {

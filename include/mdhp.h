@@ -536,6 +536,23 @@ mdhp_status mdhp_lstm_backward(const mdhp_lstm_dims* dims, const float* x, const
                                const float* dh, float* dx, float* dW, float* dU, float* dbias,
                                float* dWhks, float* dfeat, float* work, void* stream);
 
+/* Phase timing of the MDHP-LSTM passes, for profiling.  With enable = 1 the
+ * following calls of mdhp_lstm_forward and mdhp_lstm_backward record HIP
+ * events (created on the device current at the first enable) between their
+ * phases, on their stream; mdhp_lstm_phase_ms waits for the last call of
+ * each pass and writes its phase durations in ms (-1 for a pass not run
+ * since timing was enabled; either pointer may be null):
+ *   forward  [MDHP_LSTM_FWD_PHASES]: features and packing of U, the hks
+ *            GEMM, the input GEMM, the recurrence;
+ *   backward [MDHP_LSTM_BWD_PHASES]: packing of U, the recurrence (with
+ *            the bias gradient), the dx, dW and dU GEMMs, the Hawkes-gate
+ *            gradients.
+ * Process-wide state: one timing caller at a time. */
+#define MDHP_LSTM_FWD_PHASES 4
+#define MDHP_LSTM_BWD_PHASES 6
+mdhp_status mdhp_lstm_timing(int32_t enable);
+mdhp_status mdhp_lstm_phase_ms(float* fwd_ms, float* bwd_ms);
+
 /* Static description of a status code. */
 const char* mdhp_status_string(mdhp_status status);
 

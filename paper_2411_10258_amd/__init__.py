@@ -14,11 +14,11 @@ from .api import (BETA_PAIR, BETA_SHARED, FIT_CONVERGED, FIT_MAX_STEPS, FIT_NONF
                   mdhp_plan_create, mdhp_plan_destroy, mdhp_status_string)
 from .autograd import MDHPLogLik, mdhp_loglik_autograd
 from .lstm import (MDHPLSTM, MDHPLSTMFunction, mdhp_lstm_backward, mdhp_lstm_forward,
-                   mdhp_lstm_sizes)
+                   mdhp_lstm_phase_ms, mdhp_lstm_sizes, mdhp_lstm_timing)
 
 __all__ = ["Plan", "FitOptions", "MDHPLogLik", "mdhp_loglik_autograd", "MdhpError", "mdhp_plan_create", "mdhp_plan_destroy",
            "mdhp_loglik", "mdhp_grad", "mdhp_grad_static", "mdhp_simulate", "mdhp_attack_times", "mdhp_fit_batch", "mdhp_check_params", "mdhp_cold_start",
            "mdhp_status_string", "BETA_SHARED", "BETA_PAIR", "OPT_PGD", "OPT_PADAM",
            "OPT_LBFGS", "OPT_EM", "SCATTER_MFMA", "FIT_CONVERGED", "FIT_MAX_STEPS", "FIT_NONFINITE", "FIT_STALLED",
            "MDHPLSTM", "MDHPLSTMFunction", "mdhp_lstm_forward", "mdhp_lstm_backward",
-           "mdhp_lstm_sizes"]
+           "mdhp_lstm_sizes", "mdhp_lstm_timing", "mdhp_lstm_phase_ms"]

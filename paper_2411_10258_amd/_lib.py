@@ -26,6 +26,7 @@ EXPORTS = (
     "mdhp_plan_set_schedule", "mdhp_plan_schedule", "mdhp_plan_create_scheduled",
     "mdhp_surrogate_save", "mdhp_surrogate_load", "mdhp_grad_static", "mdhp_simulate",
     "mdhp_attack_times", "mdhp_lstm_sizes", "mdhp_lstm_forward", "mdhp_lstm_backward",
+    "mdhp_lstm_timing", "mdhp_lstm_phase_ms",
 )
 
 MDHP_OK = 0
@@ -37,6 +38,7 @@ SCATTER_MFMA = 1  # the M > 32 schedule with the intensity sums on the matrix co
 SIM_UNTIL_T, SIM_COUNT = 0, 1
 ATTACK_PLA, ATTACK_DEA, ATTACK_ASA, ATTACK_DAM = 0, 1, 2, 3
 SAMPLER_NPP, SAMPLER_ND, SAMPLER_DRP = 0, 1, 2
+LSTM_FWD_PHASES, LSTM_BWD_PHASES = 4, 6
 FIT_CONVERGED, FIT_MAX_STEPS, FIT_NONFINITE, FIT_STALLED = 0, 1, 2, 3
 MAX_M = 64
 TUNE_MAX = 8
@@ -136,6 +138,8 @@ def load() -> ctypes.CDLL:
     lib.mdhp_lstm_sizes.argtypes = [LD, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     lib.mdhp_lstm_forward.argtypes = [LD, P, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.mdhp_lstm_backward.argtypes = [LD, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.mdhp_lstm_timing.argtypes = [I32]
+    lib.mdhp_lstm_phase_ms.argtypes = [P, P]
     lib.mdhp_status_string.argtypes = [I32]
     lib.mdhp_status_string.restype = ctypes.c_char_p
     lib.mdhp_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
@@ -148,7 +152,7 @@ def load() -> ctypes.CDLL:
                  "mdhp_plan_autotune", "mdhp_plan_set_schedule", "mdhp_surrogate_save",
                  "mdhp_surrogate_load", "mdhp_grad_static", "mdhp_simulate",
                  "mdhp_attack_times", "mdhp_lstm_sizes", "mdhp_lstm_forward",
-                 "mdhp_lstm_backward"):
+                 "mdhp_lstm_backward", "mdhp_lstm_timing", "mdhp_lstm_phase_ms"):
         getattr(lib, name).restype = I32
     _lib = lib
     return lib

@@ -48,13 +48,21 @@ __device__ __forceinline__ float sigmoidf(float z) { return 1.f / (1.f + expf(-z
 // ----------------------------------------------------------------- GEMM
 // C[i][j] = epilogue(sum_{z < Z} sum_{k < K} A(z, i, k) B(z, k, j)) with
 // A(z, i, k) = A[z saz + i sai + k sak] and B(z, k, j) = B[z sbz + k sbk +
-// j sbj].  With S > 1 workgroup slice s of the grid sums its share of z (Z
-// > 1) or of k (Z = 1) into part[s][Mr][Nc], and gemm_reduce_kernel adds the
-// slices in order and applies the epilogue (deterministic).  Epilogue:
-// + bias[j], then tanh if act, then store or add to C.
-// Tiles: 64 x 64 per workgroup of 4 waves (2 x 2 of 32 x 32), K staged in
-// LDS 16 at a time.
-constexpr int GT = 64, GK = 16, GLD = GT + 16;  // row stride 80: 4 k-rows in distinct banks
+// j sbj].  With S > 1 grid row s sums its share of z (Z > 1) or of k (Z = 1)
+// into part[s][Mr][Nc], and gemm_reduce_kernel adds the shares in order and
+// applies the epilogue (deterministic).  Epilogue: + bias[j], then tanh if
+// act, then store or add to C.
+// Tiles: 128 x 128 per workgroup of 4 waves (2 x 2 of 64 x 64, 4 x 4 MFMA
+// blocks each), K staged in LDS 32 at a time with k contiguous per row, so
+// that a lane's A and B values for four k-steps are one float4 each (the
+// k-permuted order of the recurrent kernels: in k-group kg lane l supplies
+// k = 16 kg + 4 (l / 16) + s at step s); the next chunk's global loads are
+// issued before the current chunk's products.  Tile order: the hardware
+// deals consecutive workgroups round-robin to the 8 XCDs; each XCD is given
+// a contiguous run of row-major tiles, so that the workgroups sharing an A
+// row strip (and, for few column tiles, a B column strip) share one L2.
+constexpr int GT = 128, GK = 32, GLD = GK + 4;  // row stride 36: 16 rows in distinct banks
+constexpr int kXcds = 8;
 
 struct GemmF32 {
   const float* A;
@@ -77,12 +85,84 @@ __device__ __forceinline__ void gemm_finish(const GemmF32& g, int64_t i, int64_t
   *dst = g.accumulate ? *dst + v : v;
 }
 
+// Tile (row, column) of dispatch id x among T = nI nJ tiles.
+__device__ __forceinline__ void gemm_tile(int64_t x, int64_t nJ, int64_t T, int64_t* ti,
+                                          int64_t* tj) {
+  const int64_t q = T / kXcds, r = T % kXcds;
+  const int64_t xcd = x % kXcds, slot = x / kXcds;
+  const int64_t t = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+  *ti = t / nJ;
+  *tj = t % nJ;
+}
+
+// Staging of one operand's 128 x 32 tile: element (m, k) of the tile is
+// P[m sm + k sk] (m the tile's row or column index).  With k contiguous
+// (sk == 1) thread t loads 16 consecutive k of row t / 2; otherwise 16
+// consecutive m of k-row t % 32 (so that a wavefront's transposing LDS
+// stores spread over 32 banks).  v receives them; store() writes them to
+// LDS as T[m][k].
+struct TileStage {
+  bool kc;
+  __device__ __forceinline__ void load(const float* P, int64_t sm, int64_t sk, int64_t m0,
+                                       int64_t mlim, int64_t k0, int64_t klim, int tid,
+                                       float (&v)[16]) const {
+    // The thread's 16 elements are p[e * step], e < n (n < 16 at the tile's
+    // edges, 0 outside); a full, contiguous, 16-byte aligned run is read as
+    // four float4.
+    const float* p;
+    int64_t step, n;
+    if (kc) {
+      const int64_t m = m0 + (tid >> 1), kb = k0 + 16 * (tid & 1);
+      p = P + m * sm + kb;
+      step = sk;
+      n = m < mlim ? std::min<int64_t>(std::max<int64_t>(klim - kb, 0), 16) : 0;
+    } else {
+      const int64_t k = k0 + (tid & 31), mb = m0 + 16 * (tid >> 5);
+      p = P + mb * sm + k * sk;
+      step = sm;
+      n = k < klim ? std::min<int64_t>(std::max<int64_t>(mlim - mb, 0), 16) : 0;
+    }
+    if (n == 16 && step == 1 && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+      const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float4 w = q[e];
+        v[4 * e] = w.x;
+        v[4 * e + 1] = w.y;
+        v[4 * e + 2] = w.z;
+        v[4 * e + 3] = w.w;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = e < n ? p[e * step] : 0.f;
+    }
+  }
+  __device__ __forceinline__ void store(float (*T)[GLD], int tid, const float (&v)[16]) const {
+    if (kc) {
+      float* row = &T[tid >> 1][16 * (tid & 1)];
+#pragma unroll
+      for (int e = 0; e < 16; e += 4)
+        *reinterpret_cast<float4*>(row + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
+    } else {
+      const int k = tid & 31, mb = 16 * (tid >> 5);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) T[mb + e][k] = v[e];
+    }
+  }
+};
+
 __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmF32 g) {
-  __shared__ float As[GK][GLD];  // As[k][i]
-  __shared__ float Bs[GK][GLD];  // Bs[k][j]
+  // Two buffers: chunk c + 1 is stored while chunk c is read (one barrier
+  // per chunk).
+  __shared__ __attribute__((aligned(16))) float As[2][GT][GLD];  // As[.][i][k]
+  __shared__ __attribute__((aligned(16))) float Bs[2][GT][GLD];  // Bs[.][j][k]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t i0 = (int64_t)blockIdx.y * GT, j0 = (int64_t)blockIdx.x * GT;
-  const int s = blockIdx.z;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int64_t nI = (g.Mr + GT - 1) / GT, nJ = (g.Nc + GT - 1) / GT;
+  int64_t ti, tj;
+  gemm_tile(blockIdx.x, nJ, nI * nJ, &ti, &tj);
+  const int64_t i0 = ti * GT, j0 = tj * GT;
+  const int s = blockIdx.y;
   int64_t zb = 0, ze = g.Z, kb = 0, ke = g.K;
   if (g.S > 1) {
     if (g.Z > 1) {
@@ -93,62 +173,66 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmF32 g) {
       ke = g.K * (s + 1) / g.S;
     }
   }
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const bool a_kc = g.sak == 1;  // stage A along k, else along i
-  const bool b_jc = g.sbj == 1;  // stage B along j, else along k
-  f32x4 acc[2][2];
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const TileStage sa{g.sak == 1}, sb{g.sbk == 1};
+  f32x4 acc[4][4];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t z = zb; z < ze; ++z) {
-    const float* Az = g.A + z * g.saz;
-    const float* Bz = g.B + z * g.sbz;
-    for (int64_t k0 = kb; k0 < ke; k0 += GK) {
-      float av[4], bv[4];
-      int ai[4], ak[4], bj[4], bk[4];
+    for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int64_t kchunks = ke > kb ? (ke - kb + GK - 1) / GK : 0;
+  const int64_t nchunks = (ze - zb) * kchunks;
+  float av[16], bv[16];
+  auto fetch = [&](int64_t c) {
+    const int64_t z = zb + c / kchunks;
+    const int64_t k0 = kb + (c % kchunks) * GK;
+    sa.load(g.A + z * g.saz, g.sai, g.sak, i0, g.Mr, k0, ke, tid, av);
+    sb.load(g.B + z * g.sbz, g.sbj, g.sbk, j0, g.Nc, k0, ke, tid, bv);
+  };
+  if (nchunks > 0) {
+    fetch(0);
+    sa.store(As[0], tid, av);
+    sb.store(Bs[0], tid, bv);
+  }
+  __syncthreads();
+  for (int64_t c = 0; c < nchunks; ++c) {
+    const int cb = (int)(c & 1);
+    if (c + 1 < nchunks) fetch(c + 1);  // in flight during this chunk's products
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int idx = tid + 256 * e;  // 0 .. 1023 over a 64 x 16 tile
-        ai[e] = a_kc ? idx / GK : idx % GT;
-        ak[e] = a_kc ? idx % GK : idx / GT;
-        const int64_t gi = i0 + ai[e], gk = k0 + ak[e];
-        av[e] = (gi < g.Mr && gk < ke) ? Az[gi * g.sai + gk * g.sak] : 0.f;
-        bj[e] = b_jc ? idx % GT : idx / GK;
-        bk[e] = b_jc ? idx / GT : idx % GK;
-        const int64_t gj = j0 + bj[e], gk2 = k0 + bk[e];
-        bv[e] = (gj < g.Nc && gk2 < ke) ? Bz[gk2 * g.sbk + gj * g.sbj] : 0.f;
-      }
-      __syncthreads();  // the previous chunk's LDS reads are done
+    for (int kg = 0; kg < GK / 16; ++kg) {
+      float4 a[4], b[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        As[ak[e]][ai[e]] = av[e];
-        Bs[bk[e]][bj[e]] = bv[e];
-      }
-      __syncthreads();
+      for (int x = 0; x < 4; ++x)
+        a[x] = *reinterpret_cast<const float4*>(&As[cb][wm + 16 * x + lr][16 * kg + 4 * lq]);
 #pragma unroll
-      for (int kk = 0; kk < GK; kk += 4) {
-        const int kr = kk + (lane >> 4);
-        float a[2], b[2];
+      for (int y = 0; y < 4; ++y)
+        b[y] = *reinterpret_cast<const float4*>(&Bs[cb][wn + 16 * y + lr][16 * kg + 4 * lq]);
 #pragma unroll
-        for (int x = 0; x < 2; ++x) a[x] = As[kr][wm + 16 * x + (lane & 15)];
+      for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) b[y] = Bs[kr][wn + 16 * y + (lane & 15)];
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y) acc[x][y] = mfma4(a[x], b[y], acc[x][y]);
-      }
+        for (int y = 0; y < 4; ++y) {
+          acc[x][y] = mfma4(a[x].x, b[y].x, acc[x][y]);
+          acc[x][y] = mfma4(a[x].y, b[y].y, acc[x][y]);
+          acc[x][y] = mfma4(a[x].z, b[y].z, acc[x][y]);
+          acc[x][y] = mfma4(a[x].w, b[y].w, acc[x][y]);
+        }
     }
+    // The other buffer was last read in chunk c - 1, before the barrier
+    // that ended it.
+    if (c + 1 < nchunks) {
+      sa.store(As[cb ^ 1], tid, av);
+      sb.store(Bs[cb ^ 1], tid, bv);
+    }
+    __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < 4; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + wm + 16 * x + 4 * (lane >> 4) + r;
-        const int64_t j = j0 + wn + 16 * y + (lane & 15);
+        const int64_t i = i0 + wm + 16 * x + 4 * lq + r;
+        const int64_t j = j0 + wn + 16 * y + lr;
         if (i < g.Mr && j < g.Nc) {
           if (g.S > 1) g.part[((int64_t)s * g.Mr + i) * g.Nc + j] = acc[x][y][r];
           else gemm_finish(g, i, j, acc[x][y][r]);
@@ -166,7 +250,7 @@ __global__ void gemm_reduce_kernel(GemmF32 g) {
   }
 }
 
-constexpr int kMaxSplit = 16;
+constexpr int kMaxSplit = 64;
 
 // Splits so that tiles x splits reaches about 1,024 workgroups, each split
 // keeping at least 256 of the reduction.
@@ -182,9 +266,8 @@ hipError_t gemm_f32(GemmF32 g, float* part, hipStream_t st) {
   g.S = part ? gemm_splits(g.Mr, g.Nc, g.Z, g.K) : 1;
   g.part = part;
   if (g.Mr == 0 || g.Nc == 0) return hipSuccess;
-  const dim3 grid((unsigned)((g.Nc + GT - 1) / GT), (unsigned)((g.Mr + GT - 1) / GT),
-                  (unsigned)g.S);
-  hipLaunchKernelGGL(gemm_f32_kernel, grid, dim3(256), 0, st, g);
+  const int64_t tiles = ((g.Mr + GT - 1) / GT) * ((g.Nc + GT - 1) / GT);
+  hipLaunchKernelGGL(gemm_f32_kernel, dim3((unsigned)tiles, (unsigned)g.S), dim3(256), 0, st, g);
   if (g.S > 1) {
     const int64_t n = g.Mr * g.Nc;
     const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
@@ -261,16 +344,10 @@ __global__ void lstm_negate_block_kernel(int64_t Bn, int Kf, int c0, int nc, flo
     x[(e / nc) * Kf + c0 + e % nc] *= -1.f;
 }
 
-// part[s][j] = sum of column j of X [rows][cols] over split s's rows.
-__global__ void colsum_part_kernel(const float* __restrict__ X, int64_t rows, int cols, int S,
-                                   float* __restrict__ part) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = blockIdx.y;
-  if (j >= cols) return;
-  const int64_t r0 = rows * s / S, r1 = rows * (s + 1) / S;
-  float v = 0.f;
-  for (int64_t r = r0; r < r1; ++r) v += X[r * cols + j];
-  part[(int64_t)s * cols + j] = v;
+// out[j] = sum over s of part[s][j], in order.
+__global__ void lstm_zero_kernel(float* __restrict__ x, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) x[e] = 0.f;
 }
 
 __global__ void colsum_reduce_kernel(const float* __restrict__ part, int cols, int S,
@@ -282,189 +359,234 @@ __global__ void colsum_reduce_kernel(const float* __restrict__ part, int cols, i
   out[j] = v;
 }
 
-constexpr int kColsumSplit = 256;
-
 // ------------------------------------------------------------ recurrence
-constexpr int kRows = 16;  // sequences per workgroup (one MFMA row tile)
+// One workgroup per 16 sequences (one MFMA row tile) and one wavefront per
+// 16 hidden units: H / 16 waves (4, 8 or 16), so that a SIMD holds several
+// waves whose gate arithmetic and loads overlap the others' matrix-core
+// work.  Lane l of wave w owns unit 16 w + l % 16 of sequences
+// 4 (l / 16) .. + 3: the four result rows of its accumulators.
+constexpr int kRows = 16;
 
 // gates [B][L][4H]: on entry W x_t + b, on exit (i, f, g, o); c and h
 // [B][L][H]; hks [B][H].
 template <int H>
-__global__ __launch_bounds__(256) void lstm_fwd_kernel(int64_t Bn, int L,
-                                                       const float4* __restrict__ Up,
-                                                       const float* __restrict__ hks,
-                                                       float* __restrict__ gates,
-                                                       float* __restrict__ cs,
-                                                       float* __restrict__ hout) {
-  constexpr int UT = H / 64;  // unit tiles per wave
-  constexpr int NT = 4 * UT;  // gate-column tiles per wave
-  constexpr int KS = H / 16;  // k-groups of 16
+__global__ __launch_bounds__(4 * H) void lstm_fwd_kernel(int64_t Bn, int L,
+                                                         const float4* __restrict__ Up,
+                                                         const float* __restrict__ hks,
+                                                         float* __restrict__ gates,
+                                                         float* __restrict__ cs,
+                                                         float* __restrict__ hout) {
+  constexpr int KS = H / 16;  // k-groups of 16 over h
   constexpr int HS = H + 4;   // LDS row stride (float4-aligned)
   __shared__ __attribute__((aligned(16))) float hs[2][kRows][HS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lq = lane >> 4;
+  const int u = 16 * wave + lr;
   const int64_t r0 = (int64_t)blockIdx.x * kRows;
-  for (int e = tid; e < kRows * HS; e += 256) hs[0][e / HS][e % HS] = 0.f;
-  float hk[UT][4], c[UT][4];
+  float hk[4], c[4];
+  bool ok[4];
 #pragma unroll
-  for (int ut = 0; ut < UT; ++ut)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + 4 * lq + r;
-      const int u = (wave * UT + ut) * 16 + lr;
-      hk[ut][r] = row < Bn ? hks[row * H + u] : 0.f;
-      c[ut][r] = 0.f;
-    }
-  __syncthreads();
-  for (int t = 0; t < L; ++t) {
-    const int cur = t & 1;
-    f32x4 acc[NT];
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = r0 + 4 * lq + r;
+    ok[r] = row < Bn;
+    hk[r] = ok[r] ? hks[row * H + u] : 0.f;
+    c[r] = 0.f;
+  }
+  // Step t + 1's pre-activations are loaded during step t.
+  float nx[4][4];
+  auto load_pre = [&](int t) {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int ut = 0; ut < UT; ++ut)
+      for (int r = 0; r < 4; ++r)
+        nx[q][r] = ok[r] ? gates[((r0 + 4 * lq + r) * L + t) * (4 * H) + q * H + u] : 0.f;
+  };
+  load_pre(0);
+  for (int t = 0; t < L; ++t) {
+    const int cur = t & 1;
+    f32x4 acc[4];  // gates i, f, g, o
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t row = r0 + 4 * lq + r;
-          const int col = q * H + (wave * UT + ut) * 16 + lr;
-          acc[q * UT + ut][r] = row < Bn ? gates[(row * L + t) * (4 * H) + col] : 0.f;
-        }
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[q][r] = nx[q][r];
     if (t > 0) {
-#pragma unroll 2
+#pragma unroll 4
       for (int ks = 0; ks < KS; ++ks) {
         const float4 a = *reinterpret_cast<const float4*>(&hs[cur][lr][16 * ks + 4 * lq]);
 #pragma unroll
-        for (int n = 0; n < NT; ++n) {
-          const int q = n / UT, ut = n % UT;
-          const int ntg = q * (H / 16) + wave * UT + ut;
-          const float4 b = Up[((int64_t)ntg * KS + ks) * 64 + lane];
-          acc[n] = mfma4(a.x, b.x, acc[n]);
-          acc[n] = mfma4(a.y, b.y, acc[n]);
-          acc[n] = mfma4(a.z, b.z, acc[n]);
-          acc[n] = mfma4(a.w, b.w, acc[n]);
+        for (int q = 0; q < 4; ++q) {
+          const float4 b = Up[((int64_t)(q * (H / 16) + wave) * KS + ks) * 64 + lane];
+          acc[q] = mfma4(a.x, b.x, acc[q]);
+          acc[q] = mfma4(a.y, b.y, acc[q]);
+          acc[q] = mfma4(a.z, b.z, acc[q]);
+          acc[q] = mfma4(a.w, b.w, acc[q]);
         }
       }
     }
+    // Issued after this step's last load of U: vector-memory loads complete
+    // in order, so a prefetch issued earlier would hold up the first use of
+    // U; here the gate arithmetic and the barrier cover its latency.
+    if (t + 1 < L) load_pre(t + 1);
 #pragma unroll
-    for (int ut = 0; ut < UT; ++ut)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + 4 * lq + r;
-        const int u = (wave * UT + ut) * 16 + lr;
-        const float i = sigmoidf(acc[0 * UT + ut][r]);
-        const float f = sigmoidf(acc[1 * UT + ut][r]);
-        const float g = tanhf(acc[2 * UT + ut][r]);
-        const float o = sigmoidf(acc[3 * UT + ut][r]);
-        const float cn = hk[ut][r] * (f * c[ut][r] + i * g);
-        const float h = o * tanhf(cn);
-        c[ut][r] = cn;
-        hs[cur ^ 1][4 * lq + r][u] = row < Bn ? h : 0.f;
-        if (row < Bn) {
-          float* gp = gates + (row * L + t) * (4 * H) + u;
-          gp[0] = i;
-          gp[H] = f;
-          gp[2 * H] = g;
-          gp[3 * H] = o;
-          cs[(row * L + t) * H + u] = cn;
-          hout[(row * L + t) * H + u] = h;
-        }
+    for (int r = 0; r < 4; ++r) {
+      const float i = sigmoidf(acc[0][r]);
+      const float f = sigmoidf(acc[1][r]);
+      const float g = tanhf(acc[2][r]);
+      const float o = sigmoidf(acc[3][r]);
+      const float cn = hk[r] * (f * c[r] + i * g);
+      const float h = o * tanhf(cn);
+      c[r] = cn;
+      hs[cur ^ 1][4 * lq + r][u] = ok[r] ? h : 0.f;
+      if (ok[r]) {
+        const int64_t rt = (r0 + 4 * lq + r) * L + t;
+        float* gp = gates + rt * (4 * H) + u;
+        gp[0] = i;
+        gp[H] = f;
+        gp[2 * H] = g;
+        gp[3 * H] = o;
+        cs[rt * H + u] = cn;
+        hout[rt * H + u] = h;
       }
+    }
     __syncthreads();
   }
 }
 
 // gates [B][L][4H]: on entry (i, f, g, o), on exit dz (the gradient with
 // respect to the pre-activations); dh [B][L][H] the loss's gradient with
-// respect to each h_t; dhks [B][H] out.
+// respect to each h_t; dhks [B][H] out; dbpart [gridDim.x][4H] out: the
+// workgroup's column sums of dz (the bias gradient's share).
 template <int H>
-__global__ __launch_bounds__(256) void lstm_bwd_kernel(int64_t Bn, int L,
-                                                       const float4* __restrict__ UpT,
-                                                       const float* __restrict__ hks,
-                                                       float* __restrict__ gates,
-                                                       const float* __restrict__ cs,
-                                                       const float* __restrict__ dh,
-                                                       float* __restrict__ dhks) {
-  constexpr int UT = H / 64;      // unit tiles per wave
+__global__ __launch_bounds__(4 * H) void lstm_bwd_kernel(int64_t Bn, int L,
+                                                         const float4* __restrict__ UpT,
+                                                         const float* __restrict__ hks,
+                                                         float* __restrict__ gates,
+                                                         const float* __restrict__ cs,
+                                                         const float* __restrict__ dh,
+                                                         float* __restrict__ dhks,
+                                                         float* __restrict__ dbpart) {
   constexpr int KT = 4 * H / 16;  // k-groups over the gate columns
   constexpr int GS = 4 * H + 4;
   __shared__ __attribute__((aligned(16))) float dzs[kRows][GS];  // dz_{t+1}
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lq = lane >> 4;
+  const int u = 16 * wave + lr;
   const int64_t r0 = (int64_t)blockIdx.x * kRows;
-  float hk[UT][4], dc[UT][4], dk[UT][4];
+  float hk[4], dc[4], dk[4], db[4] = {0.f, 0.f, 0.f, 0.f};
+  bool ok[4];
 #pragma unroll
-  for (int ut = 0; ut < UT; ++ut)
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = r0 + 4 * lq + r;
+    ok[r] = row < Bn;
+    hk[r] = ok[r] ? hks[row * H + u] : 0.f;
+    dc[r] = 0.f;
+    dk[r] = 0.f;
+  }
+  // Step t's inputs (gate activations, c_{t-1}, dh_t) are loaded during step
+  // t + 1; c_t is the previous step's c_{t-1}.
+  float gi[4][4], cpn[4], dhn[4], ctv[4];
+  auto load_in = [&](int t) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + 4 * lq + r;
-      const int u = (wave * UT + ut) * 16 + lr;
-      hk[ut][r] = row < Bn ? hks[row * H + u] : 0.f;
-      dc[ut][r] = 0.f;
-      dk[ut][r] = 0.f;
-    }
-  for (int t = L - 1; t >= 0; --t) {
-    f32x4 acc[UT];
+      const int64_t rt = (r0 + 4 * lq + r) * L + t;
 #pragma unroll
-    for (int ut = 0; ut < UT; ++ut) acc[ut] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int q = 0; q < 4; ++q) gi[q][r] = ok[r] ? gates[rt * (4 * H) + q * H + u] : 0.f;
+      cpn[r] = (ok[r] && t > 0) ? cs[(rt - 1) * H + u] : 0.f;
+      dhn[r] = ok[r] ? dh[rt * H + u] : 0.f;
+    }
+  };
+#pragma unroll
+  for (int r = 0; r < 4; ++r) ctv[r] = ok[r] ? cs[((r0 + 4 * lq + r) * L + L - 1) * H + u] : 0.f;
+  load_in(L - 1);
+  for (int t = L - 1; t >= 0; --t) {
+    float iv[4], fv[4], gv[4], ov[4], cpv[4], dhv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      iv[r] = gi[0][r];
+      fv[r] = gi[1][r];
+      gv[r] = gi[2][r];
+      ov[r] = gi[3][r];
+      cpv[r] = cpn[r];
+      dhv[r] = dhn[r];
+    }
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
     if (t < L - 1) {
-#pragma unroll 2
+#pragma unroll 4
       for (int ks = 0; ks < KT; ++ks) {
         const float4 a = *reinterpret_cast<const float4*>(&dzs[lr][16 * ks + 4 * lq]);
-#pragma unroll
-        for (int ut = 0; ut < UT; ++ut) {
-          const int ntg = wave * UT + ut;
-          const float4 b = UpT[((int64_t)ntg * KT + ks) * 64 + lane];
-          acc[ut] = mfma4(a.x, b.x, acc[ut]);
-          acc[ut] = mfma4(a.y, b.y, acc[ut]);
-          acc[ut] = mfma4(a.z, b.z, acc[ut]);
-          acc[ut] = mfma4(a.w, b.w, acc[ut]);
-        }
+        const float4 b = UpT[((int64_t)wave * KT + ks) * 64 + lane];
+        acc = mfma4(a.x, b.x, acc);
+        acc = mfma4(a.y, b.y, acc);
+        acc = mfma4(a.z, b.z, acc);
+        acc = mfma4(a.w, b.w, acc);
       }
     }
+    if (t > 0) load_in(t - 1);  // after the last load of U, as in the forward kernel
     __syncthreads();  // every read of dz_{t+1} is done
 #pragma unroll
-    for (int ut = 0; ut < UT; ++ut)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + 4 * lq + r;
-        const int u = (wave * UT + ut) * 16 + lr;
-        float dzi = 0.f, dzf = 0.f, dzg = 0.f, dzo = 0.f;
-        if (row < Bn) {
-          float* gp = gates + (row * L + t) * (4 * H) + u;
-          const float i = gp[0], f = gp[H], g = gp[2 * H], o = gp[3 * H];
-          const float ct = cs[(row * L + t) * H + u];
-          const float cp = t > 0 ? cs[(row * L + t - 1) * H + u] : 0.f;
-          const float dht = dh[(row * L + t) * H + u] + acc[ut][r];
-          const float tc = tanhf(ct);
-          const float dct = dc[ut][r] + dht * o * (1.f - tc * tc);
-          const float s = f * cp + i * g;  // c_t = hks s
-          dk[ut][r] += dct * s;
-          const float ds = dct * hk[ut][r];
-          dzi = ds * g * i * (1.f - i);
-          dzf = ds * cp * f * (1.f - f);
-          dzg = ds * i * (1.f - g * g);
-          dzo = dht * tc * o * (1.f - o);
-          dc[ut][r] = ds * f;
-          gp[0] = dzi;
-          gp[H] = dzf;
-          gp[2 * H] = dzg;
-          gp[3 * H] = dzo;
-        }
-        float* zp = &dzs[4 * lq + r][u];
-        zp[0] = dzi;
-        zp[H] = dzf;
-        zp[2 * H] = dzg;
-        zp[3 * H] = dzo;
+    for (int r = 0; r < 4; ++r) {
+      float dzi = 0.f, dzf = 0.f, dzg = 0.f, dzo = 0.f;
+      if (ok[r]) {
+        const int64_t rt = (r0 + 4 * lq + r) * L + t;
+        float* gp = gates + rt * (4 * H) + u;
+        const float i = iv[r], f = fv[r], g = gv[r], o = ov[r];
+        const float ct = ctv[r];
+        const float cp = cpv[r];
+        ctv[r] = cp;  // c_{t-1} is the next step's c_t
+        const float dht = dhv[r] + acc[r];
+        const float tc = tanhf(ct);
+        const float dct = dc[r] + dht * o * (1.f - tc * tc);
+        const float s = f * cp + i * g;  // c_t = hks s
+        dk[r] += dct * s;
+        const float ds = dct * hk[r];
+        dzi = ds * g * i * (1.f - i);
+        dzf = ds * cp * f * (1.f - f);
+        dzg = ds * i * (1.f - g * g);
+        dzo = dht * tc * o * (1.f - o);
+        dc[r] = ds * f;
+        gp[0] = dzi;
+        gp[H] = dzf;
+        gp[2 * H] = dzg;
+        gp[3 * H] = dzo;
+        db[0] += dzi;
+        db[1] += dzf;
+        db[2] += dzg;
+        db[3] += dzo;
       }
+      float* zp = &dzs[4 * lq + r][u];
+      zp[0] = dzi;
+      zp[H] = dzf;
+      zp[2 * H] = dzg;
+      zp[3 * H] = dzo;
+    }
     __syncthreads();
   }
 #pragma unroll
-  for (int ut = 0; ut < UT; ++ut)
+  for (int r = 0; r < 4; ++r)
+    if (ok[r]) dhks[(r0 + 4 * lq + r) * H + u] = dk[r];
+  // Column sums over the workgroup's 16 sequences: lanes lr, lr + 16,
+  // lr + 32 and lr + 48 hold the same unit.
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + 4 * lq + r;
-      if (row < Bn) dhks[row * H + (wave * UT + ut) * 16 + lr] = dk[ut][r];
-    }
+  for (int q = 0; q < 4; ++q) {
+    float v = db[q];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (lq == 0) dbpart[(int64_t)blockIdx.x * (4 * H) + q * H + u] = v;
+  }
+}
+
+// Phase timing (profiling): HIP events recorded between the phases of the
+// last forward and backward calls, on their streams.
+struct PhaseTimer {
+  bool on = false;
+  bool made = false;
+  bool used[2] = {false, false};
+  hipEvent_t ev[2][MDHP_LSTM_BWD_PHASES + 1];
+};
+PhaseTimer g_timer;
+
+void mark(int pass, int k, hipStream_t st) {
+  if (g_timer.on) (void)hipEventRecord(g_timer.ev[pass][k], st);
 }
 
 unsigned ew_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
@@ -496,27 +618,30 @@ mdhp_status lstm_shape(const mdhp_lstm_dims* d, Shape* s) {
 int64_t saved_floats(const Shape& s) {
   return s.B * s.L * 5 * (int64_t)s.H + s.B * (int64_t)s.H + s.B * (int64_t)s.Kf;
 }
-// Workspace layout (floats): Up [4H H], UpT [4H H], GEMM partials, dhks [B][H].
+// Workspace layout (floats): Up [4H H], UpT [4H H], GEMM partials or the
+// bias gradient's per-workgroup sums, dhks [B][H].
 int64_t part_floats(const Shape& s) {
   const int64_t big = std::max<int64_t>(4 * (int64_t)s.H * std::max(s.D, s.H),
                                         (int64_t)s.H * s.Kf);
-  return std::max<int64_t>(kMaxSplit * big, (int64_t)kColsumSplit * 4 * s.H);
+  return std::max<int64_t>(kMaxSplit * big, ((s.B + kRows - 1) / kRows) * 4 * (int64_t)s.H);
 }
 int64_t work_floats(const Shape& s) {
   return 8 * (int64_t)s.H * s.H + part_floats(s) + s.B * (int64_t)s.H;
 }
 
+int64_t recurrent_groups(const Shape& s) { return (s.B + kRows - 1) / kRows; }
+
 template <int H>
 void launch_fwd(const Shape& s, const float4* Up, const float* hks, float* gates, float* cs,
                 float* h, hipStream_t st) {
-  hipLaunchKernelGGL(lstm_fwd_kernel<H>, dim3((unsigned)((s.B + kRows - 1) / kRows)), dim3(256),
-                     0, st, s.B, s.L, Up, hks, gates, cs, h);
+  hipLaunchKernelGGL(lstm_fwd_kernel<H>, dim3((unsigned)recurrent_groups(s)), dim3(4 * H), 0, st,
+                     s.B, s.L, Up, hks, gates, cs, h);
 }
 template <int H>
 void launch_bwd(const Shape& s, const float4* UpT, const float* hks, float* gates, const float* cs,
-                const float* dh, float* dhks, hipStream_t st) {
-  hipLaunchKernelGGL(lstm_bwd_kernel<H>, dim3((unsigned)((s.B + kRows - 1) / kRows)), dim3(256),
-                     0, st, s.B, s.L, UpT, hks, gates, cs, dh, dhks);
+                const float* dh, float* dhks, float* dbpart, hipStream_t st) {
+  hipLaunchKernelGGL(lstm_bwd_kernel<H>, dim3((unsigned)recurrent_groups(s)), dim3(4 * H), 0, st,
+                     s.B, s.L, UpT, hks, gates, cs, dh, dhks, dbpart);
 }
 
 }  // namespace
@@ -557,22 +682,28 @@ mdhp_status mdhp_lstm_forward(const mdhp_lstm_dims* d, const float* x, const flo
   float* feat = hks + s.B * H;
   float4* Up = reinterpret_cast<float4*>(work);
   float4* UpT = Up + H * H;
+  mark(0, 0, st);
   hipLaunchKernelGGL(lstm_features_kernel, dim3(ew_blocks(s.B * s.Kf)), dim3(256), 0, st, s.B,
                      s.M, s.Kb, alpha, beta, T_span, theta, feat);
   hipLaunchKernelGGL(lstm_pack_kernel, dim3(ew_blocks(H * H)), dim3(256), 0, st, s.H, U, Up, UpT);
+  mark(0, 1, st);
   // hks = tanh(feat [B][Kf] Whks^T)
   GemmF32 g1{feat, 0, s.Kf, 1, Whks, 0, 1, s.Kf, 1, s.Kf, s.B, H, hks, H,
              nullptr, nullptr, 1, 0, 1};
   hipError_t he = gemm_f32(g1, nullptr, st);
+  mark(0, 2, st);
   // gates = x [BL][D] W^T + b
   GemmF32 g2{x, 0, s.D, 1, W, 0, 1, s.D, 1, s.D, BL, G, gates, G, nullptr, bias, 0, 0, 1};
   if (he == hipSuccess) he = gemm_f32(g2, nullptr, st);
   if (he != hipSuccess) return mdhp_hip_fail(he, "lstm_forward");
+  mark(0, 3, st);
   switch (s.H) {
     case 64: launch_fwd<64>(s, Up, hks, gates, cs, h, st); break;
     case 128: launch_fwd<128>(s, Up, hks, gates, cs, h, st); break;
     default: launch_fwd<256>(s, Up, hks, gates, cs, h, st); break;
   }
+  mark(0, 4, st);
+  if (g_timer.on) g_timer.used[0] = true;
   he = hipGetLastError();
   return he == hipSuccess ? MDHP_OK : mdhp_hip_fail(he, "lstm_forward");
 }
@@ -599,33 +730,49 @@ mdhp_status mdhp_lstm_backward(const mdhp_lstm_dims* d, const float* x, const fl
   float4* UpT = Up + H * H;
   float* part = work + 8 * H * H;
   float* dpre = part + part_floats(s);
-  if (s.B > 0) {
+  mark(1, 0, st);
+  if (s.B > 0)
     hipLaunchKernelGGL(lstm_pack_kernel, dim3(ew_blocks(H * H)), dim3(256), 0, st, s.H, U, Up,
                        UpT);
+  mark(1, 1, st);
+  if (s.B > 0) {
     switch (s.H) {
-      case 64: launch_bwd<64>(s, UpT, hks, dz, cs, dh, dpre, st); break;
-      case 128: launch_bwd<128>(s, UpT, hks, dz, cs, dh, dpre, st); break;
-      default: launch_bwd<256>(s, UpT, hks, dz, cs, dh, dpre, st); break;
+      case 64: launch_bwd<64>(s, UpT, hks, dz, cs, dh, dpre, part, st); break;
+      case 128: launch_bwd<128>(s, UpT, hks, dz, cs, dh, dpre, part, st); break;
+      default: launch_bwd<256>(s, UpT, hks, dz, cs, dh, dpre, part, st); break;
     }
-    hipLaunchKernelGGL(lstm_dpre_kernel, dim3(ew_blocks(s.B * H)), dim3(256), 0, st, s.B * H, hks,
-                       dpre);
   }
+  // db = sum of the workgroups' column sums, while they are in the workspace
+  const int nG = (int)recurrent_groups(s);
+  if (nG > 0)
+    hipLaunchKernelGGL(colsum_reduce_kernel, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, st,
+                       part, (int)G, nG, dbias);
+  else
+    hipLaunchKernelGGL(lstm_zero_kernel, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, st,
+                       dbias, G);
+  mark(1, 2, st);
   hipError_t he = hipGetLastError();
   // dx [BL][D] = dZ [BL][4H] W [4H][D]
   if (he == hipSuccess)
     he = gemm_f32(GemmF32{dz, 0, G, 1, W, 0, s.D, 1, 1, G, BL, s.D, dx, s.D, nullptr, nullptr,
                           0, 0, 1},
                   nullptr, st);
+  mark(1, 3, st);
   // dW [4H][D] = dZ^T X
   if (he == hipSuccess)
     he = gemm_f32(GemmF32{dz, 0, 1, G, x, 0, s.D, 1, 1, BL, G, s.D, dW, s.D, nullptr, nullptr,
                           0, 0, 1},
                   part, st);
+  mark(1, 4, st);
   // dU [4H][H] = sum over sequences b and steps t >= 1 of dz[b][t]^T h[b][t-1]
   if (he == hipSuccess)
     he = gemm_f32(GemmF32{dz + G, (int64_t)s.L * G, 1, G, h, (int64_t)s.L * H, H, 1, s.B,
                           s.L - 1, G, H, dU, H, nullptr, nullptr, 0, 0, 1},
                   part, st);
+  mark(1, 5, st);
+  if (s.B > 0)
+    hipLaunchKernelGGL(lstm_dpre_kernel, dim3(ew_blocks(s.B * H)), dim3(256), 0, st, s.B * H, hks,
+                       dpre);
   // dWhks [H][Kf] = dpre^T feat (feat carries -beta T_span: this is dB itself)
   if (he == hipSuccess)
     he = gemm_f32(GemmF32{dpre, 0, 1, H, feat, 0, s.Kf, 1, 1, s.B, H, s.Kf, dWhks, s.Kf, nullptr,
@@ -640,14 +787,42 @@ mdhp_status mdhp_lstm_backward(const mdhp_lstm_dims* d, const float* x, const fl
   if (s.B > 0)
     hipLaunchKernelGGL(lstm_negate_block_kernel, dim3(ew_blocks(s.B * s.Kb)), dim3(256), 0, st,
                        s.B, s.Kf, s.M * s.M, s.Kb, dfeat);
-  // db = column sums of dZ
-  const int S = (int)std::max<int64_t>(1, std::min<int64_t>(kColsumSplit, BL / 64));
-  hipLaunchKernelGGL(colsum_part_kernel, dim3((unsigned)((G + 255) / 256), (unsigned)S),
-                     dim3(256), 0, st, dz, BL, (int)G, S, part);
-  hipLaunchKernelGGL(colsum_reduce_kernel, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, st,
-                     part, (int)G, S, dbias);
+  mark(1, 6, st);
+  if (g_timer.on) g_timer.used[1] = true;
   he = hipGetLastError();
   return he == hipSuccess ? MDHP_OK : mdhp_hip_fail(he, "lstm_backward");
+}
+
+mdhp_status mdhp_lstm_timing(int32_t enable) {
+  if (enable && !g_timer.made) {
+    for (auto& pass : g_timer.ev)
+      for (hipEvent_t& e : pass) {
+        const hipError_t he = hipEventCreate(&e);
+        if (he != hipSuccess) return mdhp_hip_fail(he, "lstm_timing");
+      }
+    g_timer.made = true;
+  }
+  g_timer.on = enable != 0;
+  g_timer.used[0] = g_timer.used[1] = false;
+  return MDHP_OK;
+}
+
+mdhp_status mdhp_lstm_phase_ms(float* fwd_ms, float* bwd_ms) {
+  if (!g_timer.made) return mdhp_fail(MDHP_E_INVAL, "lstm_phase_ms: timing was never enabled");
+  const int n[2] = {MDHP_LSTM_FWD_PHASES, MDHP_LSTM_BWD_PHASES};
+  float* out[2] = {fwd_ms, bwd_ms};
+  for (int p = 0; p < 2; ++p) {
+    if (!out[p]) continue;
+    if (!g_timer.used[p]) {
+      for (int k = 0; k < n[p]; ++k) out[p][k] = -1.f;
+      continue;
+    }
+    hipError_t he = hipEventSynchronize(g_timer.ev[p][n[p]]);
+    for (int k = 0; he == hipSuccess && k < n[p]; ++k)
+      he = hipEventElapsedTime(&out[p][k], g_timer.ev[p][k], g_timer.ev[p][k + 1]);
+    if (he != hipSuccess) return mdhp_hip_fail(he, "lstm_phase_ms");
+  }
+  return MDHP_OK;
 }
 
 }  // extern "C"

@@ -19,8 +19,11 @@ import torch
 from . import _lib
 from .api import _ptr, _stream
 
-__all__ = ["mdhp_lstm_sizes", "mdhp_lstm_forward", "mdhp_lstm_backward", "MDHPLSTMFunction",
-           "MDHPLSTM"]
+__all__ = ["mdhp_lstm_sizes", "mdhp_lstm_forward", "mdhp_lstm_backward", "mdhp_lstm_timing",
+           "mdhp_lstm_phase_ms", "MDHPLSTMFunction", "MDHPLSTM"]
+
+FWD_PHASES = ("prepare", "hks_gemm", "input_gemm", "recurrence")
+BWD_PHASES = ("prepare", "recurrence", "dx_gemm", "dW_gemm", "dU_gemm", "hawkes_gate")
 
 
 def _dims(B, L, D, H, M, beta_mode) -> _lib.MdhpLstmDims:
@@ -93,6 +96,19 @@ def mdhp_lstm_backward(x, W, U, Whks, h, saved, work, dh, M, beta_mode, stream=N
         _ptr(out["dx"]), _ptr(out["dW"]), _ptr(out["dU"]), _ptr(out["dbias"]),
         _ptr(out["dWhks"]), _ptr(out["dfeat"]), _ptr(work), ctypes.c_void_p(_stream(stream))))
     return out
+
+
+def mdhp_lstm_timing(enable: bool) -> None:
+    """Record HIP events between the phases of later forward/backward calls."""
+    _lib.check(_lib.load().mdhp_lstm_timing(int(bool(enable))))
+
+
+def mdhp_lstm_phase_ms() -> tuple[dict, dict]:
+    """Phase durations (ms) of the last timed forward and backward calls."""
+    f = (ctypes.c_float * _lib.LSTM_FWD_PHASES)()
+    b = (ctypes.c_float * _lib.LSTM_BWD_PHASES)()
+    _lib.check(_lib.load().mdhp_lstm_phase_ms(f, b))
+    return dict(zip(FWD_PHASES, list(f))), dict(zip(BWD_PHASES, list(b)))
 
 
 class MDHPLSTMFunction(torch.autograd.Function):

@@ -7,10 +7,10 @@ buffers' sizes for ragged and full shapes."""
 
 import pytest
 
-GT = 64
-MAX_SPLIT = 16
-COLSUM_SPLIT = 256
+GT = 128
+MAX_SPLIT = 64
 ROWS = 16
+XCDS = 8
 
 
 def splits(Mr, Nc, Z, K):
@@ -25,7 +25,7 @@ def sizes(B, L, D, H, M, pair):
     Kb = M * M if pair else 1
     Kf = M * M + Kb + M
     saved = B * L * 5 * H + B * H + B * Kf
-    part = max(MAX_SPLIT * max(4 * H * max(D, H), H * Kf), COLSUM_SPLIT * 4 * H)
+    part = max(MAX_SPLIT * max(4 * H * max(D, H), H * Kf), -(-B // ROWS) * 4 * H)
     work = 8 * H * H + part + B * H
     return Kf, Kb, saved, part, work
 
@@ -74,25 +74,21 @@ def model(B, L, D, H, M, pair):
                part, True)
     check_gemm("dfeat", (0, 0, H, 1, B * H), (0, 0, Kf, 1, H * Kf), (Kf, B * Kf), 1, H, B, Kf,
                part, False)
-    S = max(1, min(COLSUM_SPLIT, BL // 64))
-    assert S * G <= part
+    # the bias gradient's per-workgroup column sums
+    assert -(-B // ROWS) * G <= part
     # packed copies of U: H*H float4 each, indexes (nt KS + ks) 64 + lane
     KS, KT = H // 16, G // 16
-    assert (G // 16 - 1) * KS * 64 + (KS - 1) * 64 + 63 < H * H
-    assert (H // 16 - 1) * KT * 64 + (KT - 1) * 64 + 63 < H * H
     # the rows U rows / columns the packing reads
     assert 16 * (KS - 1) + 4 * 3 + 3 < H and 16 * (KT - 1) + 4 * 3 + 3 < G
-    # recurrent kernels: rows < B, t < L, col < 4H, unit < H
-    UT = H // 64
-    for wave in range(4):
-        for ut in range(UT):
-            u_max = (wave * UT + ut) * 16 + 15
-            assert u_max < H
-            assert 3 * H + u_max < G
-            # forward n-tiles and backward n-tiles inside the packed copies
-            for q in range(4):
-                assert q * (H // 16) + wave * UT + ut < G // 16
-            assert wave * UT + ut < H // 16
+    # recurrent kernels: H / 16 waves, wave w owns units 16 w .. 16 w + 15;
+    # rows < B, t < L, col < 4H
+    for wave in range(H // 16):
+        u_max = 16 * wave + 15
+        assert u_max < H and 3 * H + u_max < G
+        for q in range(4):  # forward: Up[((q (H/16) + w) KS + ks) 64 + lane]
+            assert ((q * (H // 16) + wave) * KS + KS - 1) * 64 + 63 < H * H
+        assert ((wave * KT) + KT - 1) * 64 + 63 < H * H  # backward: UpT
+    assert 4 * H <= 1024  # threads per workgroup
     if B:
         last = ((B - 1) * L + L - 1)
         assert last * G + G - 1 < BL * G and last * H + H - 1 < BL * H
@@ -118,3 +114,17 @@ def test_split_partials_fit_for_every_gemm():
         for D in (1, 17, 256, 1024):
             for B in (1, 15, 16, 4096):
                 model(B, 3, D, H, 8, False)
+
+
+def gemm_tile(x, nJ, T):
+    q, r = divmod(T, XCDS)
+    xcd, slot = x % XCDS, x // XCDS
+    t = xcd * (q + 1) + slot if xcd < r else r * (q + 1) + (xcd - r) * q + slot
+    return divmod(t, nJ)
+
+
+@pytest.mark.parametrize("nI,nJ", [(1, 1), (1, 3), (5, 2), (8, 2), (13, 7), (4096, 8)])
+def test_gemm_tile_order_is_a_permutation(nI, nJ):
+    T = nI * nJ
+    seen = {gemm_tile(x, nJ, T) for x in range(T)}
+    assert seen == {(i, j) for i in range(nI) for j in range(nJ)}
