@@ -294,7 +294,8 @@ def bench_lstm(args, dev) -> int:
         "phase_ms": avg,
         "step_tflops": total_flops / (ms * 1e-3) / 1e12,
         "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
+                     "traffic": read_traffic("lstm." + top, "mdhp_lstm.hip"),
                      "kernel": top, "flops_per_launch": flops[top]},
     }
     if not args.no_cpu:

@@ -181,7 +181,7 @@ def test_attack_drp_counts(gpu):
     for _ in range(400):
         w = np.array([g.uniform(0, 1 / 3), g.uniform(1 / 3, 2 / 3), g.uniform(2 / 3, 1)])[third]
         gv = w * 3.0 * grid ** 2 + (1.0 - w) * 4.0 * np.exp(4.0 * grid)
-        exp_n.append(r * np.trapz(gv, grid) / gv.max())
+        exp_n.append(r * np.trapezoid(gv, grid) / gv.max())
     assert abs(n.mean() - np.mean(exp_n)) <= 0.03 * np.mean(exp_n)
 
 
