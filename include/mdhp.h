@@ -304,6 +304,13 @@ mdhp_status mdhp_plan_set_schedule(mdhp_plan* plan, const mdhp_batch* batch, int
 /* The plan's current schedule value (0 for kind 0 or a NULL plan). */
 int32_t mdhp_plan_schedule(const mdhp_plan* plan);
 
+/* Events per window and dimension as the plan counted them at creation
+ * (the N_m of the cold start, Sec. IV-B): counts [W][M] int32, device
+ * memory, caller-owned, in the batch's window order.  Enqueued on stream
+ * (a device-to-device copy); MDHP_E_INVAL for an invalid plan or a null
+ * pointer with W > 0. */
+mdhp_status mdhp_plan_dim_counts(const mdhp_plan* plan, int32_t* counts, void* stream);
+
 /* mdhp_plan_create with a schedule chosen beforehand (a candidate of the
  * plan's kind, e.g. from an earlier mdhp_plan_autotune of the same batch
  * shape; 0 = default), prepared once in that layout.  MDHP_E_INVAL for a
@@ -543,7 +550,8 @@ mdhp_status mdhp_lstm_backward(const mdhp_lstm_dims* dims, const float* x, const
  * each pass and writes its phase durations in ms (-1 for a pass not run
  * since timing was enabled; either pointer may be null):
  *   forward  [MDHP_LSTM_FWD_PHASES]: features and packing of U, the hks
- *            GEMM, the input GEMM, the recurrence;
+ *            GEMM, the input GEMM (for D <= 256, where the recurrence forms
+ *            the input products itself: the packing of W), the recurrence;
  *   backward [MDHP_LSTM_BWD_PHASES]: packing of U, the recurrence (with
  *            the bias gradient), the dx, dW and dU GEMMs, the Hawkes-gate
  *            gradients.

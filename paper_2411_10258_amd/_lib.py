@@ -26,7 +26,7 @@ EXPORTS = (
     "mdhp_plan_set_schedule", "mdhp_plan_schedule", "mdhp_plan_create_scheduled",
     "mdhp_surrogate_save", "mdhp_surrogate_load", "mdhp_grad_static", "mdhp_simulate",
     "mdhp_attack_times", "mdhp_lstm_sizes", "mdhp_lstm_forward", "mdhp_lstm_backward",
-    "mdhp_lstm_timing", "mdhp_lstm_phase_ms",
+    "mdhp_lstm_timing", "mdhp_lstm_phase_ms", "mdhp_plan_dim_counts",
 )
 
 MDHP_OK = 0
@@ -109,6 +109,7 @@ def load() -> ctypes.CDLL:
     lib.mdhp_plan_create_scheduled.argtypes = [ctypes.POINTER(MdhpBatch), I32, I32, I32, P,
                                                ctypes.POINTER(P)]
     lib.mdhp_plan_create_scheduled.restype = I32
+    lib.mdhp_plan_dim_counts.argtypes = [P, P, P]
     lib.mdhp_plan_schedule.argtypes = [P]
     lib.mdhp_plan_schedule.restype = I32
     lib.mdhp_features.argtypes = [ctypes.POINTER(MdhpBatch), I32, I32, P, P]
@@ -152,7 +153,8 @@ def load() -> ctypes.CDLL:
                  "mdhp_plan_autotune", "mdhp_plan_set_schedule", "mdhp_surrogate_save",
                  "mdhp_surrogate_load", "mdhp_grad_static", "mdhp_simulate",
                  "mdhp_attack_times", "mdhp_lstm_sizes", "mdhp_lstm_forward",
-                 "mdhp_lstm_backward", "mdhp_lstm_timing", "mdhp_lstm_phase_ms"):
+                 "mdhp_lstm_backward", "mdhp_lstm_timing", "mdhp_lstm_phase_ms",
+                 "mdhp_plan_dim_counts"):
         getattr(lib, name).restype = I32
     _lib = lib
     return lib

@@ -352,6 +352,13 @@ class Plan:
     def schedule(self) -> int:
         return mdhp_plan_schedule(self.handle)
 
+    def dim_counts(self, stream=None) -> torch.Tensor:
+        """Events per window and dimension, int32 [W, M] on the plan's device."""
+        out = torch.empty((self.W, self.M), dtype=torch.int32, device=self.device)
+        _lib.check(_lib.load().mdhp_plan_dim_counts(ctypes.c_void_p(self.handle), _ptr(out),
+                                                    ctypes.c_void_p(_stream(stream))))
+        return out
+
     def check_params(self, mu, alpha, beta, stream=None) -> None:
         mu, alpha, beta = self._params(mu, alpha, beta)
         mdhp_check_params(self.handle, mu, alpha, beta, stream)

@@ -628,6 +628,16 @@ mdhp_status mdhp_plan_set_schedule(mdhp_plan* p, const mdhp_batch* b, int32_t va
   return apply_schedule(p, b, value, (hipStream_t)stream);
 }
 
+mdhp_status mdhp_plan_dim_counts(const mdhp_plan* p, int32_t* counts, void* stream) {
+  if (!plan_ok(p)) return fail(MDHP_E_INVAL, "dim_counts: invalid plan");
+  const int64_t n = p->W * (int64_t)p->M;
+  if (n == 0) return MDHP_OK;
+  if (!counts) return fail(MDHP_E_INVAL, "dim_counts: null pointer");
+  const hipError_t e = hipMemcpyAsync(counts, p->counts, n * sizeof(int32_t),
+                                      hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  return e == hipSuccess ? MDHP_OK : hip_fail(e, "dim_counts");
+}
+
 int32_t mdhp_plan_schedule(const mdhp_plan* p) {
   if (!plan_ok(p) || p->beta_mode != MDHP_BETA_SHARED) return 0;
   return p->lane_major ? (int32_t)std::min<int64_t>(p->big_min, MDHP_TEAM_NEVER) : p->scatter;

@@ -1,7 +1,9 @@
 """Training and evaluation pipeline of the learned warm start.
 
-1. Simulate training windows (seeded Ogata thinning) and fit each from the
-   cold start with the GPU solver; the fitted parameters are the targets.
+1. Simulate training windows (seeded Ogata thinning: parameters drawn on
+   the host, events by the library's device simulator, the same windows as
+   the host generator's) and fit each from the cold start with the GPU
+   solver; the fitted parameters are the targets.
 2. Compute the windows' count-histogram features on the GPU and train the
    network (BF16 MFMA forward/backward, Adam) on z-scored log-parameters.
 3. On held-out windows, fit from the cold start and from the warm start
@@ -16,14 +18,16 @@ from __future__ import annotations
 
 import time
 from dataclasses import dataclass, field
+from types import SimpleNamespace
 
 import numpy as np
 import torch
 
 import synth
 
-from .api import BETA_SHARED, FIT_CONVERGED, FIT_STALLED, OPT_LBFGS, FitOptions, Plan
-from .surrogate import (BINS, Surrogate, TargetStats, dim_counts, features, log_targets,
+from .api import (BETA_SHARED, FIT_CONVERGED, FIT_STALLED, OPT_LBFGS, FitOptions, Plan,
+                  mdhp_simulate)
+from .surrogate import (BINS, Surrogate, TargetStats, features, log_targets,
                         warm_start)
 
 DEFAULT_FIT = dict(max_steps=1000, optimizer=OPT_LBFGS, ll_tol=1e-7, history=8)
@@ -51,6 +55,16 @@ def make_batch(M: int, W: int, seed: int, first: int = 0):
     raise ValueError("warm-start workloads exist for M = 16 and M = 64")
 
 
+def make_device_batch(M: int, W: int, seed: int, first: int = 0, device="cuda") -> DeviceBatch:
+    """Windows first..first+W-1 of the M = 16 or M = 64 workload with the
+    events simulated on the device (parameters and counts from
+    synth.shared_params); `b` carries M, W and the event count only."""
+    mu, al, be, counts = synth.shared_params(M, W, seed, first)
+    off, t, dim, T = mdhp_simulate(mu, al, be, counts=counts, seed=seed, first_window=first,
+                                   device=device)
+    return DeviceBatch(SimpleNamespace(M=M, W=W, n_events=int(counts.sum())), off, t, dim, T)
+
+
 def fit_cold(db: DeviceBatch, opts: FitOptions):
     b = db.b
     plan = Plan(db.offsets, db.t, db.dim, db.T, b.M, BETA_SHARED)
@@ -70,27 +84,40 @@ class TrainingSet:
     info: dict = field(default_factory=dict)
 
 
-def build_training_set(M: int, n_windows: int, seed: int = 1024, chunk: int = 4096,
-                       opts: FitOptions | None = None, log=None) -> TrainingSet:
+def build_training_set(M: int, n_windows: int, seed: int = 1024, chunk: int = 0,
+                       opts: FitOptions | None = None, log=None,
+                       device_sim: bool = True) -> TrainingSet:
+    """Features and fitted targets of windows 0..n_windows-1 of (M, seed),
+    in chunks (default 65,536 windows at M = 16 and 4,096 at M = 64 with
+    device simulation, 4,096 with the host generator)."""
     opts = opts or FitOptions(**DEFAULT_FIT)
+    chunk = chunk or (4096 if (not device_sim or M == 64) else 65536)
     xs, ys, oks = [], [], []
     gen_s = fit_s = 0.0
     for first in range(0, n_windows, chunk):
         W = min(chunk, n_windows - first)
         t0 = time.perf_counter()
-        b = make_batch(M, W, seed, first)
+        if device_sim:
+            db = make_device_batch(M, W, seed, first)
+            torch.cuda.synchronize()
+        else:
+            db = DeviceBatch.of(make_batch(M, W, seed, first))
         t1 = time.perf_counter()
-        db = DeviceBatch.of(b)
-        mu, al, be, ll, st, stat, ev = fit_cold(db, opts)
+        plan = Plan(db.offsets, db.t, db.dim, db.T, M, BETA_SHARED)
+        mu0, al0, be0 = plan.cold_start()
+        mu, al, be, ll, st, stat, ev = plan.fit(mu0, al0, be0, opts, return_evals=True)
+        Nm = plan.dim_counts()
         torch.cuda.synchronize()
+        plan.close()
         t2 = time.perf_counter()
         gen_s += t1 - t0
         fit_s += t2 - t1
         stat = stat.cpu().numpy()
         xs.append(features(db.offsets, db.t, db.dim, db.T, M))
         ys.append(log_targets(M, mu.cpu().numpy(), al.cpu().numpy(), be.cpu().numpy(),
-                              dim_counts(b.offsets, b.dim, M), b.T))
+                              Nm.cpu().numpy(), db.T.cpu().numpy()))
         oks.append((stat == FIT_CONVERGED) | (stat == FIT_STALLED))
+        del db
         if log:
             log(f"training windows {first + W}/{n_windows}: sim {t1 - t0:.1f}s fit {t2 - t1:.2f}s")
     return TrainingSet(torch.cat(xs), np.concatenate(ys), np.concatenate(oks), gen_s, fit_s)

@@ -210,11 +210,43 @@ def single_m4(seed: int = 2024, nthreads: int = 0) -> Batch:
     return Batch(M, 0, off, t, d, T, mu, alpha, beta, name="single_m4")
 
 
+# Parameter and count distributions of the shared-decay workloads (arguments
+# of _draw_shared after M).
+SHARED_DISTS = {16: (0.05, 1.0, 0.2, 0.8, (0.5, 1.0, 2.0), 1000.0, 1.0, 100, 20000),
+                64: (0.05, 1.0, 0.2, 0.8, (0.5, 1.0, 2.0), 5000.0, 1.2, 500, 50000)}
+
+
+def _draw_chunk(task):
+    seed, lo, hi, M = task
+    return _draw_shared(seed, np.arange(lo, hi), M, *SHARED_DISTS[M])
+
+
+def shared_params(M: int, W: int, seed: int = 2024, first: int = 0, workers: int = 0):
+    """(mu, alpha, beta, counts) of windows first..first+W-1 of the M = 16
+    or M = 64 workload: the values batch_m16 / large_m64 simulate, for a
+    caller that simulates the events itself (e.g. on the device).  Each
+    window's draw depends only on (seed, window), so chunks drawn by
+    `workers` processes (0: os.cpu_count(), capped at 8) give the same
+    values.  The workers are fresh interpreters ("spawn"), so they hold no
+    handle of a GPU the caller may have opened."""
+    workers = workers or min(8, os.cpu_count() or 1)
+    chunk = 16384
+    tasks = [(seed, lo, min(lo + chunk, first + W), M) for lo in range(first, first + W, chunk)]
+    if workers <= 1 or len(tasks) <= 1:
+        parts = [_draw_chunk(t) for t in tasks]
+    else:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(min(workers, len(tasks))) as pool:
+            parts = pool.map(_draw_chunk, tasks)
+    if not parts:
+        return (np.zeros((0, M)), np.zeros((0, M, M)), np.zeros(0), np.zeros(0, np.int64))
+    return tuple(np.concatenate([p[k] for p in parts]) for k in range(4))
+
+
 def batch_m16(W: int = 4096, seed: int = 2024, first: int = 0, nthreads: int = 0) -> Batch:
     """Windows first..first+W-1 of the M=16 shared-decay workload."""
     windows = np.arange(first, first + W)
-    mu, alpha, beta, counts = _draw_shared(seed, windows, 16, 0.05, 1.0, 0.2, 0.8,
-                                           (0.5, 1.0, 2.0), 1000.0, 1.0, 100, 20000)
+    mu, alpha, beta, counts = _draw_shared(seed, windows, 16, *SHARED_DISTS[16])
     off, t, d, T = _simulate_windows(16, 0, mu, alpha, beta, counts, seed, windows, nthreads)
     return Batch(16, 0, off, t, d, T, mu, alpha, beta, name="batch_m16")
 
@@ -222,8 +254,7 @@ def batch_m16(W: int = 4096, seed: int = 2024, first: int = 0, nthreads: int = 0
 def large_m64(W: int = 16384, seed: int = 2024, first: int = 0, nthreads: int = 0) -> Batch:
     """Windows first..first+W-1 of the M=64 shared-decay workload."""
     windows = np.arange(first, first + W)
-    mu, alpha, beta, counts = _draw_shared(seed, windows, 64, 0.05, 1.0, 0.2, 0.8,
-                                           (0.5, 1.0, 2.0), 5000.0, 1.2, 500, 50000)
+    mu, alpha, beta, counts = _draw_shared(seed, windows, 64, *SHARED_DISTS[64])
     off, t, d, T = _simulate_windows(64, 0, mu, alpha, beta, counts, seed, windows, nthreads)
     return Batch(64, 0, off, t, d, T, mu, alpha, beta, name="large_m64")
 
@@ -233,8 +264,7 @@ def streams_m16(S: int = 1024, n_events: int = 2304, seed: int = 2025, nthreads:
     M=16 batch workload's (one decay per stream in {0.5, 1, 2}), n_events
     events each: the input of sliding-window fitting."""
     streams = np.arange(S)
-    mu, alpha, beta, _ = _draw_shared(seed, streams, 16, 0.05, 1.0, 0.2, 0.8,
-                                      (0.5, 1.0, 2.0), 1000.0, 1.0, 100, 20000)
+    mu, alpha, beta, _ = _draw_shared(seed, streams, 16, *SHARED_DISTS[16])
     counts = np.full(S, n_events, np.int64)
     off, t, d, T = _simulate_windows(16, 0, mu, alpha, beta, counts, seed, streams, nthreads)
     return Batch(16, 0, off, t, d, T, mu, alpha, beta, name="streams_m16")

@@ -210,3 +210,20 @@ def test_invalid_inputs_are_reported(gpu):
     for rng in ([1.0, 0.0], [0.0, np.inf], [np.nan, 1.0], [0.0, 1e6]):
         with pytest.raises(gpu.MdhpError):
             gpu.mdhp_attack_times([0], [0], p[None, :], np.array([rng]), [64], seed=1)
+
+
+def test_device_training_batch_matches_host_batch(gpu, synth_lib):
+    """The warm-start pipeline's device-simulated batch equals the host
+    generator's windows, and the plan's per-dimension counts equal a count
+    of the host events."""
+    from paper_2411_10258_amd import surrogate, warmstart
+    db = warmstart.make_device_batch(16, 64, seed=1024, first=100)
+    hb = synth_lib.batch_m16(W=64, seed=1024, first=100)
+    off, t, d = _host(db.offsets), _host(db.t), _host(db.dim)
+    assert np.array_equal(off, hb.offsets)
+    same = _same_windows(off, t, d, hb.offsets, hb.t, hb.dim)
+    assert same.mean() >= 0.95
+    plan = gpu.Plan(db.offsets, db.t, db.dim, db.T, 16, gpu.BETA_SHARED)
+    counts = _host(plan.dim_counts())
+    plan.close()
+    assert np.array_equal(counts, surrogate.dim_counts(off, d, 16).astype(np.int32))

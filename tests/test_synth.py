@@ -89,3 +89,18 @@ def test_mean_counts_match_stationary_rate(synth_lib):
     se = counts.std(0) / np.sqrt(W)
     # Transient from an empty history lowers the mean by O(1) events only.
     assert np.all(np.abs(mean - rates * 400.0) <= 4 * se + 5)
+
+
+def test_shared_params_match_the_simulated_workloads():
+    """synth.shared_params gives the parameters and counts batch_m16 and
+    large_m64 simulate, serially and from parallel workers alike."""
+    import synth
+    b = synth.batch_m16(W=40, seed=1024, first=7)
+    mu, al, be, n = synth.shared_params(16, 40, seed=1024, first=7, workers=1)
+    assert np.array_equal(mu, b.mu) and np.array_equal(al, b.alpha) and np.array_equal(be, b.beta)
+    assert np.array_equal(n, np.diff(b.offsets))
+    big = synth.shared_params(16, 40000, seed=1024, first=0, workers=2)
+    assert all(np.array_equal(x[7:47], y) for x, y in zip(big, (mu, al, be, n)))
+    b64 = synth.large_m64(W=3, seed=5, first=2)
+    mu64, al64, be64, n64 = synth.shared_params(64, 3, seed=5, first=2)
+    assert np.array_equal(al64, b64.alpha) and np.array_equal(n64, np.diff(b64.offsets))
