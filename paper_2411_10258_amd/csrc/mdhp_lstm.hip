@@ -8,8 +8,10 @@
 //   c_t = hks * (f c_{t-1} + i g),  h_t = o tanh(c_t),  h_{-1} = c_{-1} = 0.
 //
 // Work split:
-//  * the input products W x_t + b of all steps, and hks, are GEMMs before the
-//    recurrence (gemm_f32_kernel);
+//  * hks is a GEMM before the recurrence (gemm_f32_kernel); so are the input
+//    products W x_t + b of all steps for inputs wider than kFusedMaxD,
+//    while narrower inputs have them formed inside the recurrence
+//    (lstm_fwd_fused_kernel);
 //  * the recurrence (lstm_fwd_kernel): one workgroup per 16 sequences runs
 //    all L steps; h_{t-1} U^T on the matrix cores (v_mfma_f32_16x16x4_f32)
 //    with h_{t-1} in LDS and U streamed from L2 in a lane-packed layout, so
@@ -326,6 +328,26 @@ __global__ void lstm_pack_kernel(int H, const float* __restrict__ U, float4* __r
   }
 }
 
+// Lane-packed copy of W [4H][D] for the fused forward recurrence, zero-padded
+// to Dp columns: Wp[(nt KSD + ks) 64 + l] = W[q H + 16 ut + l % 16][16 ks +
+// 4 (l / 16) + s], s = 0..3, nt = q (H / 16) + ut, KSD = Dp / 16.
+__global__ void lstm_pack_w_kernel(int H, int D, int Dp, const float* __restrict__ W,
+                                   float4* __restrict__ Wp) {
+  const int64_t n = (int64_t)H * Dp;  // float4 entries
+  const int KSD = Dp / 16;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int l = (int)(e & 63);
+    const int64_t tile = e >> 6;
+    const int nt = (int)(tile / KSD), ks = (int)(tile % KSD);
+    const int q = nt / (H / 16), ut = nt % (H / 16);
+    const float* row = W + (int64_t)(q * H + 16 * ut + (l & 15)) * D;
+    const int k = 16 * ks + 4 * (l >> 4);
+    Wp[e] = make_float4(k < D ? row[k] : 0.f, k + 1 < D ? row[k + 1] : 0.f,
+                        k + 2 < D ? row[k + 2] : 0.f, k + 3 < D ? row[k + 3] : 0.f);
+  }
+}
+
 // dpre = dhks (1 - hks^2), in place.
 __global__ void lstm_dpre_kernel(int64_t n, const float* __restrict__ hks, float* __restrict__ d) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
@@ -448,6 +470,145 @@ __global__ __launch_bounds__(4 * H) void lstm_fwd_kernel(int64_t Bn, int L,
         hout[rt * H + u] = h;
       }
     }
+    __syncthreads();
+  }
+}
+
+// The forward recurrence with the input products folded in (inputs of at
+// most kFusedMaxD features): each step also forms x_t W^T + b on the matrix
+// cores, x_t staged in LDS (double-buffered, zero-padded to Dp, a multiple
+// of 16) and W read from L2 in the same lane-packed layout as U, so that
+// the pre-activations are never written to or read from HBM.  Outputs as
+// lstm_fwd_kernel's; `gates` is written only.
+constexpr int kFusedMaxD = 256;
+
+template <int H>
+__global__ __launch_bounds__(4 * H) void lstm_fwd_fused_kernel(
+    int64_t Bn, int L, int D, int Dp, const float* __restrict__ x, const float4* __restrict__ Wp,
+    const float* __restrict__ bias, const float4* __restrict__ Up, const float* __restrict__ hks,
+    float* __restrict__ gates, float* __restrict__ cs, float* __restrict__ hout) {
+  constexpr int KS = H / 16;  // k-groups of 16 over h
+  constexpr int HS = H + 4;   // LDS row stride (float4-aligned)
+  constexpr int NT = 4 * H;   // threads
+  // The 16 x Dp tile of x_t in float4 chunks: chunk c = tid + NT j is row
+  // c / (Dp / 4), features 4 (c % (Dp / 4)) .. + 3 (fixed over the steps).
+  constexpr int kMaxX = (kRows * kFusedMaxD / 4 + NT - 1) / NT;
+  __shared__ __attribute__((aligned(16))) float hs[2][kRows][HS];
+  extern __shared__ __attribute__((aligned(16))) float xs[];  // [2][kRows][Dp + 4]
+  const int XS = Dp + 4, KSD = Dp / 16, QD = Dp / 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int u = 16 * wave + lr;
+  const int64_t r0 = (int64_t)blockIdx.x * kRows;
+  float hk[4], c[4], bq[4];
+  bool ok[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = r0 + 4 * lq + r;
+    ok[r] = row < Bn;
+    hk[r] = ok[r] ? hks[row * H + u] : 0.f;
+    c[r] = 0.f;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) bq[q] = bias[q * H + u];
+  // Chunk j: its row's x at t = 0 from its first feature, the features in
+  // range (0..4; 0 for a row past the batch) and its LDS offset in a buffer
+  // (-1: no chunk).
+  const float* xp[kMaxX];
+  int xl[kMaxX], xn[kMaxX];
+#pragma unroll
+  for (int j = 0; j < kMaxX; ++j) {
+    const int cidx = tid + NT * j;
+    const int row = cidx / QD, d = 4 * (cidx % QD);
+    const bool in = cidx < kRows * QD && r0 + row < Bn;
+    xp[j] = in ? x + (r0 + row) * (int64_t)L * D + d : x;
+    xn[j] = in ? min(max(D - d, 0), 4) : 0;
+    xl[j] = cidx < kRows * QD ? row * XS + d : -1;
+  }
+  // rows of x are 16-byte aligned
+  const bool vec = (D & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+  float4 xv[kMaxX];
+  auto load_x = [&](int t) {
+#pragma unroll
+    for (int j = 0; j < kMaxX; ++j) {
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      const float* p = xp[j] + (int64_t)t * D;
+      if (xn[j] == 4 && vec) {
+        v = *reinterpret_cast<const float4*>(p);
+      } else if (xn[j] > 0) {
+        v.x = p[0];
+        if (xn[j] > 1) v.y = p[1];
+        if (xn[j] > 2) v.z = p[2];
+        if (xn[j] > 3) v.w = p[3];
+      }
+      xv[j] = v;
+    }
+  };
+  auto store_x = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < kMaxX; ++j)
+      if (xl[j] >= 0) *reinterpret_cast<float4*>(xs + buf * kRows * XS + xl[j]) = xv[j];
+  };
+  load_x(0);
+  store_x(0);
+  __syncthreads();
+  for (int t = 0; t < L; ++t) {
+    const int cur = t & 1;
+    f32x4 acc[4];  // gates i, f, g, o
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = f32x4{bq[q], bq[q], bq[q], bq[q]};
+    const float* xr = xs + (cur * kRows + lr) * XS + 4 * lq;
+#pragma unroll 4
+    for (int ks = 0; ks < KSD; ++ks) {
+      const float4 a = *reinterpret_cast<const float4*>(xr + 16 * ks);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 b = Wp[((int64_t)(q * (H / 16) + wave) * KSD + ks) * 64 + lane];
+        acc[q] = mfma4(a.x, b.x, acc[q]);
+        acc[q] = mfma4(a.y, b.y, acc[q]);
+        acc[q] = mfma4(a.z, b.z, acc[q]);
+        acc[q] = mfma4(a.w, b.w, acc[q]);
+      }
+    }
+    if (t > 0) {
+#pragma unroll 4
+      for (int ks = 0; ks < KS; ++ks) {
+        const float4 a = *reinterpret_cast<const float4*>(&hs[cur][lr][16 * ks + 4 * lq]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 b = Up[((int64_t)(q * (H / 16) + wave) * KS + ks) * 64 + lane];
+          acc[q] = mfma4(a.x, b.x, acc[q]);
+          acc[q] = mfma4(a.y, b.y, acc[q]);
+          acc[q] = mfma4(a.z, b.z, acc[q]);
+          acc[q] = mfma4(a.w, b.w, acc[q]);
+        }
+      }
+    }
+    // After the step's last load of W and U (loads complete in order).
+    if (t + 1 < L) load_x(t + 1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float i = sigmoidf(acc[0][r]);
+      const float f = sigmoidf(acc[1][r]);
+      const float g = tanhf(acc[2][r]);
+      const float o = sigmoidf(acc[3][r]);
+      const float cn = hk[r] * (f * c[r] + i * g);
+      const float h = o * tanhf(cn);
+      c[r] = cn;
+      hs[cur ^ 1][4 * lq + r][u] = ok[r] ? h : 0.f;
+      if (ok[r]) {
+        const int64_t rt = (r0 + 4 * lq + r) * L + t;
+        float* gp = gates + rt * (4 * H) + u;
+        gp[0] = i;
+        gp[H] = f;
+        gp[2 * H] = g;
+        gp[3 * H] = o;
+        cs[rt * H + u] = cn;
+        hout[rt * H + u] = h;
+      }
+    }
+    // x tile buffer cur ^ 1 was last read in step t - 1, before its barrier.
+    if (t + 1 < L) store_x(cur ^ 1);
     __syncthreads();
   }
 }
@@ -594,6 +755,7 @@ unsigned ew_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<i
 struct Shape {
   int64_t B;
   int L, D, H, M, Kb, Kf;
+  int Dp;  // padded input width of the fused forward recurrence (0: input GEMM)
 };
 
 mdhp_status lstm_shape(const mdhp_lstm_dims* d, Shape* s) {
@@ -610,6 +772,7 @@ mdhp_status lstm_shape(const mdhp_lstm_dims* d, Shape* s) {
   s->M = d->M;
   s->Kb = d->beta_mode == MDHP_BETA_PAIR ? d->M * d->M : 1;
   s->Kf = d->M * d->M + s->Kb + d->M;
+  s->Dp = d->D <= kFusedMaxD ? (d->D + 15) / 16 * 16 : 0;
   return MDHP_OK;
 }
 
@@ -618,15 +781,16 @@ mdhp_status lstm_shape(const mdhp_lstm_dims* d, Shape* s) {
 int64_t saved_floats(const Shape& s) {
   return s.B * s.L * 5 * (int64_t)s.H + s.B * (int64_t)s.H + s.B * (int64_t)s.Kf;
 }
-// Workspace layout (floats): Up [4H H], UpT [4H H], GEMM partials or the
-// bias gradient's per-workgroup sums, dhks [B][H].
+// Workspace layout (floats): Up [4H H], UpT [4H H], Wp [4H Dp], GEMM
+// partials or the bias gradient's per-workgroup sums, dhks [B][H].
 int64_t part_floats(const Shape& s) {
   const int64_t big = std::max<int64_t>(4 * (int64_t)s.H * std::max(s.D, s.H),
                                         (int64_t)s.H * s.Kf);
   return std::max<int64_t>(kMaxSplit * big, ((s.B + kRows - 1) / kRows) * 4 * (int64_t)s.H);
 }
+int64_t pack_floats(const Shape& s) { return 8 * (int64_t)s.H * s.H + 4 * (int64_t)s.H * s.Dp; }
 int64_t work_floats(const Shape& s) {
-  return 8 * (int64_t)s.H * s.H + part_floats(s) + s.B * (int64_t)s.H;
+  return pack_floats(s) + part_floats(s) + s.B * (int64_t)s.H;
 }
 
 int64_t recurrent_groups(const Shape& s) { return (s.B + kRows - 1) / kRows; }
@@ -636,6 +800,14 @@ void launch_fwd(const Shape& s, const float4* Up, const float* hks, float* gates
                 float* h, hipStream_t st) {
   hipLaunchKernelGGL(lstm_fwd_kernel<H>, dim3((unsigned)recurrent_groups(s)), dim3(4 * H), 0, st,
                      s.B, s.L, Up, hks, gates, cs, h);
+}
+template <int H>
+void launch_fwd_fused(const Shape& s, const float* x, const float4* Wp, const float* bias,
+                      const float4* Up, const float* hks, float* gates, float* cs, float* h,
+                      hipStream_t st) {
+  const size_t lds = (size_t)2 * kRows * (s.Dp + 4) * sizeof(float);
+  hipLaunchKernelGGL(lstm_fwd_fused_kernel<H>, dim3((unsigned)recurrent_groups(s)), dim3(4 * H),
+                     lds, st, s.B, s.L, s.D, s.Dp, x, Wp, bias, Up, hks, gates, cs, h);
 }
 template <int H>
 void launch_bwd(const Shape& s, const float4* UpT, const float* hks, float* gates, const float* cs,
@@ -692,15 +864,29 @@ mdhp_status mdhp_lstm_forward(const mdhp_lstm_dims* d, const float* x, const flo
              nullptr, nullptr, 1, 0, 1};
   hipError_t he = gemm_f32(g1, nullptr, st);
   mark(0, 2, st);
-  // gates = x [BL][D] W^T + b
-  GemmF32 g2{x, 0, s.D, 1, W, 0, 1, s.D, 1, s.D, BL, G, gates, G, nullptr, bias, 0, 0, 1};
-  if (he == hipSuccess) he = gemm_f32(g2, nullptr, st);
-  if (he != hipSuccess) return mdhp_hip_fail(he, "lstm_forward");
-  mark(0, 3, st);
-  switch (s.H) {
-    case 64: launch_fwd<64>(s, Up, hks, gates, cs, h, st); break;
-    case 128: launch_fwd<128>(s, Up, hks, gates, cs, h, st); break;
-    default: launch_fwd<256>(s, Up, hks, gates, cs, h, st); break;
+  if (s.Dp) {
+    // the input products run inside the recurrence
+    if (he != hipSuccess) return mdhp_hip_fail(he, "lstm_forward");
+    float4* Wp = UpT + H * H;
+    hipLaunchKernelGGL(lstm_pack_w_kernel, dim3(ew_blocks(H * s.Dp)), dim3(256), 0, st, s.H, s.D,
+                       s.Dp, W, Wp);
+    mark(0, 3, st);
+    switch (s.H) {
+      case 64: launch_fwd_fused<64>(s, x, Wp, bias, Up, hks, gates, cs, h, st); break;
+      case 128: launch_fwd_fused<128>(s, x, Wp, bias, Up, hks, gates, cs, h, st); break;
+      default: launch_fwd_fused<256>(s, x, Wp, bias, Up, hks, gates, cs, h, st); break;
+    }
+  } else {
+    // gates = x [BL][D] W^T + b
+    GemmF32 g2{x, 0, s.D, 1, W, 0, 1, s.D, 1, s.D, BL, G, gates, G, nullptr, bias, 0, 0, 1};
+    if (he == hipSuccess) he = gemm_f32(g2, nullptr, st);
+    if (he != hipSuccess) return mdhp_hip_fail(he, "lstm_forward");
+    mark(0, 3, st);
+    switch (s.H) {
+      case 64: launch_fwd<64>(s, Up, hks, gates, cs, h, st); break;
+      case 128: launch_fwd<128>(s, Up, hks, gates, cs, h, st); break;
+      default: launch_fwd<256>(s, Up, hks, gates, cs, h, st); break;
+    }
   }
   mark(0, 4, st);
   if (g_timer.on) g_timer.used[0] = true;
@@ -728,7 +914,7 @@ mdhp_status mdhp_lstm_backward(const mdhp_lstm_dims* d, const float* x, const fl
   const float* feat = hks + s.B * H;
   float4* Up = reinterpret_cast<float4*>(work);
   float4* UpT = Up + H * H;
-  float* part = work + 8 * H * H;
+  float* part = work + pack_floats(s);
   float* dpre = part + part_floats(s);
   mark(1, 0, st);
   if (s.B > 0)

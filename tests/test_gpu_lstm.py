@@ -66,12 +66,16 @@ def _grad_errors(out, g, keys):
 
 
 CASES = {
-    # B not a multiple of the 16 sequences a workgroup runs; D ragged against the 16-wide K chunks
+    # B not a multiple of the 16 sequences a workgroup runs; D ragged against
+    # the 16-wide K chunks (D <= 256: the input products inside the recurrence)
     "h64_m4_ragged": (11, 20, 7, 40, 64, 4, False),
     "h128_m3_pair": (12, 37, 5, 33, 128, 3, True),
     "h256_m16": (13, 18, 9, 256, 256, 16, False),
     "h256_m5_pair_long": (14, 17, 40, 24, 256, 5, True),
     "single_step": (15, 3, 1, 1, 64, 1, False),
+    # inputs wider than 256 features: the input products as a separate GEMM
+    "h64_wide_input": (19, 21, 3, 300, 64, 2, False),
+    "h256_wide_input": (20, 5, 4, 520, 256, 3, True),
 }
 
 

@@ -11,6 +11,7 @@ GT = 128
 MAX_SPLIT = 64
 ROWS = 16
 XCDS = 8
+FUSED_MAX_D = 256
 
 
 def splits(Mr, Nc, Z, K):
@@ -26,7 +27,8 @@ def sizes(B, L, D, H, M, pair):
     Kf = M * M + Kb + M
     saved = B * L * 5 * H + B * H + B * Kf
     part = max(MAX_SPLIT * max(4 * H * max(D, H), H * Kf), -(-B // ROWS) * 4 * H)
-    work = 8 * H * H + part + B * H
+    Dp = -(-D // 16) * 16 if D <= FUSED_MAX_D else 0
+    work = 8 * H * H + 4 * H * Dp + part + B * H
     return Kf, Kb, saved, part, work
 
 
@@ -97,8 +99,24 @@ def model(B, L, D, H, M, pair):
     assert 15 * HS + 16 * (KS - 1) + 4 * 3 + 3 < ROWS * HS
     assert 15 * GS + 16 * (KT - 1) + 4 * 3 + 3 < ROWS * GS
     assert HS % 4 == 0 and GS % 4 == 0
-    # workspace: Up, UpT, partials, dhks
-    assert 8 * H * H + part + B * H == work
+    # fused forward recurrence (D <= 256): packed W of H * Dp float4 after
+    # Up and UpT; float4 chunks of the x tile; LDS x tile [2][16][Dp + 4]
+    Dp = -(-D // 16) * 16 if D <= FUSED_MAX_D else 0
+    if Dp:
+        KSD, QD, XS = Dp // 16, Dp // 4, Dp + 4
+        for wave in range(H // 16):
+            for q in range(4):
+                assert ((q * (H // 16) + wave) * KSD + KSD - 1) * 64 + 63 < H * Dp
+        for c in range(16 * QD):  # chunk c: row c // QD, features 4 (c % QD) ..
+            row, d = divmod(c, QD)
+            d *= 4
+            n = min(max(D - d, 0), 4)
+            assert row < 16 and d + 3 < XS and (n == 0 or d + n - 1 < D)
+        assert 15 * XS + 4 * 3 + 16 * (KSD - 1) + 3 < 16 * XS
+        assert 2 * 16 * XS * 4 <= 65536  # dynamic LDS of the x tile
+        # the W packing reads columns k .. k + 3 only where k + s < D
+    # workspace: Up, UpT, Wp, partials, dhks
+    assert 8 * H * H + 4 * H * Dp + part + B * H == work
 
 
 @pytest.mark.parametrize("B,L,D,H,M,pair", [
