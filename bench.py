@@ -387,6 +387,55 @@ def bench_c4(args, dev) -> int:
     return 0
 
 
+def bench_sim(args, dev) -> int:
+    """sim_m64: device simulation (mdhp_simulate, Ogata thinning) of the
+    16,384-window M = 64 workload, parameters and counts drawn on the host
+    beforehand (untimed); one launch per step.  The host generator (the
+    independent implementation the simulator's parity tests use) is timed
+    on a sample of the same windows."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2411_10258_amd as mdhp
+
+    W = args.windows or 16384
+    mu, al, be, counts = synth.shared_params(64, W, seed=2024)
+    mu_d, al_d, be_d = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (mu, al, be))
+    n_events = int(counts.sum())
+    for _ in range(args.warmup):
+        mdhp.mdhp_simulate(mu_d, al_d, be_d, counts=counts, seed=2024, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        off, t, d, T = mdhp.mdhp_simulate(mu_d, al_d, be_d, counts=counts, seed=2024, device=dev)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    out = {
+        "metric": "MDHP window simulation events/s (Ogata thinning)", "value": n_events / (ms * 1e-3),
+        "unit": "events/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (the M=64 workload's parameters, seed 2024)",
+        "config": {"workload": f"sim_m64: {W} windows, M=64, one decay per window, "
+                               f"{n_events} events (count mode)", "global_batch": W,
+                   "parallelism": "none (1 GPU)"},
+        "roofline": None,
+    }
+    if not args.no_cpu:
+        threads = min(16, os.cpu_count() or 1)
+        k = min(W, 4096)
+        t0 = time.perf_counter()
+        synth.simulate(64, 0, mu[:k], al[:k], be[:k], counts=counts[:k], seed=2024,
+                       nthreads=threads)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": float(counts[:k].sum()) / dt, "unit": "events/s",
+                               "cores": threads, "kind": "host generator",
+                               "sample": f"the first {k} windows ({int(counts[:k].sum())} "
+                                         f"events), {dt:.1f} s"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def host_info() -> dict:
     """Host CPU of the run: logical CPUs and the model name."""
     model = ""
@@ -647,7 +696,7 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=["large_m64", "batch_m16", "pair_m32", "mdhp_lstm",
-                                           "c4_warmstart"],
+                                           "c4_warmstart", "sim_m64"],
                     default="large_m64",
                     help="large_m64: warm vs cold fits of 16,384 M=64 windows (~151M events, "
                          "default; the M=16 batch follows as extra keys unless --no-m16); "
@@ -656,7 +705,8 @@ def main() -> int:
                          "with per-pair decays; mdhp_lstm: the MDHP-LSTM layer's forward and "
                          "backward over 4,096 sequences of 128 steps; c4_warmstart: the "
                          "warm start trained on 1M device-simulated windows, evaluated on "
-                         "8,192 held-out windows")
+                         "8,192 held-out windows; sim_m64: device simulation of the M=64 "
+                         "workload's events")
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--windows", type=int, default=0, help="0: the workload's size")
@@ -715,6 +765,8 @@ def main() -> int:
         return bench_lstm(args, dev)
     if args.workload == "c4_warmstart":
         return bench_c4(args, dev)
+    if args.workload == "sim_m64":
+        return bench_sim(args, dev)
     log = lambda m: print(m, file=sys.stderr, flush=True)
     r = run_fit_workload(args, args.workload, dev, log, cpu=not args.no_cpu)
     out = {
