@@ -79,8 +79,8 @@ struct GemmArgs {
 };
 
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
-  __shared__ __bf16 As[GB_M][GB_KP];  // [row][k]
-  __shared__ __bf16 Bs[GB_N][GB_KP];  // [col][k] (B transposed)
+  __shared__ __attribute__((aligned(16))) __bf16 As[GB_M][GB_KP];  // [row][k]
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[GB_N][GB_KP];  // [col][k] (B transposed)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i0 = blockIdx.y * GB_M, j0 = blockIdx.x * GB_N;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -89,15 +89,26 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // Staging of the 64 x 32 tiles: thread t owns row t / 4, k = 8 (t % 4) .. + 7
+  // of each.  Where k is contiguous in memory and the 8 elements are in range
+  // and 16-byte aligned they are one 16-byte load, else 8 element loads.
+  const int sr = tid >> 2, sk = 8 * (tid & 3);
+  auto stage = [&](const __bf16* P, int64_t sm, int64_t skk, int m, int mlim, int k0,
+                   __bf16 (*T)[GB_KP]) {
+    const __bf16* p = P + (int64_t)m * sm + (int64_t)(k0 + sk) * skk;
+    const bool full = m < mlim && k0 + sk + 8 <= g.K;
+    if (full && skk == 1 && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+      *reinterpret_cast<bf16x8*>(&T[sr][sk]) = *reinterpret_cast<const bf16x8*>(p);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        T[sr][sk + e] = (m < mlim && k0 + sk + e < g.K) ? p[e * skk] : to_bf16(0.f);
+    }
+  };
   for (int k0 = 0; k0 < g.K; k0 += GB_K) {
     // Stage A (64 x 32) and B^T (64 x 32): 2048 elements each, 8 per thread.
-    for (int e = tid; e < GB_M * GB_K; e += 256) {
-      const int r = e / GB_K, k = e % GB_K;
-      const int gi = i0 + r, gk = k0 + k;
-      As[r][k] = (gi < g.Mr && gk < g.K) ? g.A[gi * g.sai + gk * g.sak] : to_bf16(0.f);
-      const int gj = j0 + r;
-      Bs[r][k] = (gj < g.Nc && gk < g.K) ? g.B[gk * g.sbk + gj * g.sbj] : to_bf16(0.f);
-    }
+    stage(g.A, g.sai, g.sak, i0 + sr, g.Mr, k0, As);
+    stage(g.B, g.sbj, g.sbk, j0 + sr, g.Nc, k0, Bs);
     __syncthreads();
     const int kf = 8 * (lane >> 4);
 #pragma unroll
@@ -137,14 +148,23 @@ __global__ void relu_grad_kernel(const __bf16* __restrict__ dH, const __bf16* __
     dZ[i] = from_bf16(H[i]) > 0.f ? dH[i] : to_bf16(0.f);
 }
 
-// db[j] = sum_i dZ[i][j] (one thread per column; columns are few).
-__global__ void colsum_kernel(const __bf16* __restrict__ dZ, int rows, int cols,
-                              float* __restrict__ db) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cols) return;
+// db[j] = sum_i dZ[i][j]: one workgroup per 64 columns, wavefront w summing
+// rows w, w + 4, ... (each row's 64 columns one 128-byte read), the four
+// partial sums added in order.
+constexpr int kColsumCols = 64;
+__global__ __launch_bounds__(256) void colsum_kernel(const __bf16* __restrict__ dZ, int rows,
+                                                     int cols, float* __restrict__ db) {
+  __shared__ float part[4][kColsumCols];
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * kColsumCols + c;
   float s = 0.f;
-  for (int i = 0; i < rows; ++i) s += from_bf16(dZ[(int64_t)i * cols + j]);
-  db[j] = s;
+  if (j < cols) {
+#pragma unroll 8
+    for (int i = w; i < rows; i += 4) s += from_bf16(dZ[(int64_t)i * cols + j]);
+  }
+  part[w][c] = s;
+  __syncthreads();
+  if (w == 0 && j < cols) db[j] = ((part[0][c] + part[1][c]) + part[2][c]) + part[3][c];
 }
 
 // Mean squared error over B x O and its gradient 2 (y - t) / (B O) (BF16);
@@ -487,7 +507,7 @@ mdhp_status mdhp_surrogate_backward(mdhp_surrogate* s, const uint16_t* xin, int3
   if (e == hipSuccess)
     e = gemm(s->dy, 1, O, s->h2, H, 1, O, H, B, nullptr, 0, g + s->woff[2], nullptr, H, st);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(colsum_kernel, dim3((O + 255) / 256), dim3(256), 0, st, s->dy, B, O,
+    hipLaunchKernelGGL(colsum_kernel, dim3((O + kColsumCols - 1) / kColsumCols), dim3(256), 0, st, s->dy, B, O,
                        g + s->boff[2]);
     e = gemm(s->dy, O, 1, s->wb + s->woff[2], H, 1, B, H, O, nullptr, 0, nullptr, s->dh, H, st);
   }
@@ -499,7 +519,7 @@ mdhp_status mdhp_surrogate_backward(mdhp_surrogate* s, const uint16_t* xin, int3
     e = gemm(s->dz, 1, H, s->h1, H, 1, H, H, B, nullptr, 0, g + s->woff[1], nullptr, H, st);
   }
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(colsum_kernel, dim3((H + 255) / 256), dim3(256), 0, st, s->dz, B, H,
+    hipLaunchKernelGGL(colsum_kernel, dim3((H + kColsumCols - 1) / kColsumCols), dim3(256), 0, st, s->dz, B, H,
                        g + s->boff[1]);
     e = gemm(s->dz, H, 1, s->wb + s->woff[1], H, 1, B, H, H, nullptr, 0, nullptr, s->dh, H, st);
   }
@@ -510,7 +530,7 @@ mdhp_status mdhp_surrogate_backward(mdhp_surrogate* s, const uint16_t* xin, int3
     e = gemm(s->dz, 1, H, x, I, 1, H, I, B, nullptr, 0, g + s->woff[0], nullptr, I, st);
   }
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(colsum_kernel, dim3((H + 255) / 256), dim3(256), 0, st, s->dz, B, H,
+    hipLaunchKernelGGL(colsum_kernel, dim3((H + kColsumCols - 1) / kColsumCols), dim3(256), 0, st, s->dz, B, H,
                        g + s->boff[0]);
     e = hipGetLastError();
   }
