@@ -84,3 +84,48 @@ def test_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libmdhp.so"))
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def test_host_error_paths_of_the_simulator_and_the_lstm():
+    """Argument checks that run before any device call."""
+    from paper_2411_10258_amd import _lib
+    lib = _lib.load()
+    buf = ctypes.create_string_buffer(256)
+    d = ctypes.c_void_p(16)
+    # simulate: bad sizes, decay or simulation mode; per-pair decays above 32 dims
+    assert lib.mdhp_simulate(-1, 4, 0, d, d, d, 1, None, d, 1, 0, d, d, d, d, None) == -1
+    assert lib.mdhp_simulate(2, 65, 0, d, d, d, 1, None, d, 1, 0, d, d, d, d, None) == -1
+    assert lib.mdhp_simulate(2, 33, 1, d, d, d, 1, None, d, 1, 0, d, d, d, d, None) == -1
+    assert lib.mdhp_simulate(2, 4, 0, d, d, d, 5, None, d, 1, 0, d, d, d, d, None) == -1
+    assert lib.mdhp_simulate(2, 4, 0, d, d, d, 0, None, d, 1, 0, d, d, d, d, None) == -1
+    assert lib.mdhp_last_error(buf, 256) == -1 and b"null pointer" in buf.value
+    assert lib.mdhp_simulate(0, 4, 0, None, None, None, 1, None, None, 1, 0, None, None, None,
+                             None, None) == 0
+    assert lib.mdhp_attack_times(-1, d, d, d, d, d, 1, 0, d, d, None) == -1
+    assert lib.mdhp_attack_times(3, None, d, d, d, d, 1, 0, d, d, None) == -1
+    assert lib.mdhp_attack_times(0, None, None, None, None, None, 1, 0, None, None, None) == 0
+    assert lib.mdhp_plan_dim_counts(None, d, None) == -1
+    # MDHP-LSTM: dimensions, null pointers, the empty forward pass
+    saved, work = ctypes.c_int64(), ctypes.c_int64()
+    for B, L, D, H, M, mode in ((4, 3, 5, 96, 2, 0), (4, 0, 5, 64, 2, 0), (-1, 3, 5, 64, 2, 0),
+                                (4, 3, 5, 64, 65, 0), (4, 3, 5, 64, 2, 3), (4, 3, 0, 64, 2, 0)):
+        dims = _lib.MdhpLstmDims(B, L, D, H, M, mode)
+        assert lib.mdhp_lstm_sizes(ctypes.byref(dims), ctypes.byref(saved),
+                                   ctypes.byref(work)) == -1
+    dims = _lib.MdhpLstmDims(4096, 128, 256, 256, 16, 0)
+    assert lib.mdhp_lstm_sizes(ctypes.byref(dims), ctypes.byref(saved), ctypes.byref(work)) == 0
+    Kf = 16 * 16 + 1 + 16
+    assert saved.value == 4096 * 128 * 5 * 256 + 4096 * 256 + 4096 * Kf
+    pair = _lib.MdhpLstmDims(8, 2, 3, 64, 4, 1)
+    s_pair = ctypes.c_int64()
+    assert lib.mdhp_lstm_sizes(ctypes.byref(pair), ctypes.byref(s_pair), ctypes.byref(work)) == 0
+    assert s_pair.value == 8 * 2 * 5 * 64 + 8 * 64 + 8 * (16 + 16 + 4)
+    assert lib.mdhp_lstm_sizes(None, ctypes.byref(saved), ctypes.byref(work)) == -1
+    args = [d] * 12
+    assert lib.mdhp_lstm_forward(ctypes.byref(dims), *([None] + args[1:]), None) == -1
+    assert lib.mdhp_last_error(buf, 256) == -1 and b"null pointer" in buf.value
+    empty = _lib.MdhpLstmDims(0, 3, 5, 64, 2, 0)
+    assert lib.mdhp_lstm_forward(ctypes.byref(empty), *([None] * 12), None) == 0
+    assert lib.mdhp_lstm_backward(ctypes.byref(dims), *([None] * 14), None) == -1
+    # with B = 0 the weight arrays are still required
+    assert lib.mdhp_lstm_backward(ctypes.byref(empty), *([None] * 14), None) == -1

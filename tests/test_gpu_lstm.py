@@ -169,3 +169,41 @@ def test_lstm_autograd_module(gpu):
         assert err <= G_TOL, name
     err = np.abs(layer.U.grad.cpu().numpy() - g["dU"]).max() / np.abs(g["dU"]).max()
     assert err <= G_TOL
+
+
+def test_lstm_graph_replays_match_eager(gpu):
+    """The forward and backward passes captured in one HIP graph (no memory
+    sets inside: every buffer the kernels clear is written by a kernel):
+    three replays, with eager work and synchronisation between them, each
+    equal to the eager pass bit for bit (the kernels are deterministic)."""
+    import torch
+    from synth import lstm_inputs
+    B, L, D, H, M = 20, 6, 40, 64, 4
+    c = lstm_inputs.case(21, B, L, D, H, M)
+    args = [_t(a) for a in (c.x, c.W, c.U, c.bias, c.Whks, c.alpha, c.beta, c.T_span, c.theta)]
+    dh = _t(c.dh)
+
+    def passes():
+        h, saved, work = gpu.mdhp_lstm_forward(*args)
+        g = gpu.mdhp_lstm_backward(args[0], args[1], args[2], args[4], h, saved, work, dh, M, 0)
+        return h, g
+
+    h_e, g_e = passes()
+    torch.cuda.synchronize()
+    ref = [h_e.cpu()] + [g_e[k].cpu() for k in sorted(g_e)]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        passes()  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        h_g, g_g = passes()
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        got = [h_g.cpu()] + [g_g[k].cpu() for k in sorted(g_g)]
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), f"replay {rep}"
+        passes()  # eager work between replays
+        torch.cuda.synchronize()
