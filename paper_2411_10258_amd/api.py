@@ -127,6 +127,18 @@ def mdhp_grad_static(batch, M: int, mu, alpha, beta, ll, g_mu=None, g_alpha=None
         *(None if g is None else _ptr(g) for g in grads), ctypes.c_void_p(_stream(stream))))
 
 
+def _first_slots(room_off: torch.Tensor, n: torch.Tensor) -> torch.Tensor:
+    """Host indexes of the first n[w] slots of each window's room
+    [room_off[w], room_off[w+1]), window by window."""
+    W = n.numel()
+    if W == 0:
+        return torch.zeros(0, dtype=torch.int64)
+    win = torch.repeat_interleave(torch.arange(W), n)
+    start = torch.zeros(W, dtype=torch.int64)
+    torch.cumsum(n[:-1], 0, out=start[1:])
+    return room_off[:-1][win] + (torch.arange(win.numel()) - start[win])
+
+
 def mdhp_simulate(mu, alpha, beta, *, counts=None, T_end=None, cap=None, seed: int = 2024,
                   first_window: int = 0, device="cuda", stream=None):
     """Ogata thinning on the device for W windows (mdhp_simulate).
@@ -150,10 +162,10 @@ def mdhp_simulate(mu, alpha, beta, *, counts=None, T_end=None, cap=None, seed: i
     else:
         mode, room = _lib.SIM_UNTIL_T, torch.as_tensor(cap, dtype=torch.int64)
         T_in = torch.as_tensor(T_end).to(**f64).contiguous()
-    off = torch.zeros(W + 1, dtype=torch.int64)
-    torch.cumsum(room.cpu(), 0, out=off[1:])
-    total = int(off[-1])
-    off = off.to(dev)
+    off_h = torch.zeros(W + 1, dtype=torch.int64)
+    torch.cumsum(room.cpu(), 0, out=off_h[1:])
+    total = int(off_h[-1])
+    off = off_h.to(dev)
     t = torch.zeros(total, **f64)
     dim = torch.zeros(total, dtype=torch.int32, device=dev)
     n_out = torch.zeros(W, dtype=torch.int64, device=dev)
@@ -171,9 +183,7 @@ def mdhp_simulate(mu, alpha, beta, *, counts=None, T_end=None, cap=None, seed: i
         raise MdhpError(-1, "simulate: a window has more events than its room (cap)")
     if mode == _lib.SIM_COUNT:
         return off, t, dim, T_out
-    keep = torch.cat([torch.arange(int(off[w]), int(off[w]) + int(n[w])) for w in range(W)]) \
-        if W else torch.zeros(0, dtype=torch.int64)
-    keep = keep.to(dev)
+    keep = _first_slots(off_h, n).to(dev)
     off_c = torch.zeros(W + 1, dtype=torch.int64)
     torch.cumsum(n, 0, out=off_c[1:])
     return off_c.to(dev), t[keep], dim[keep], T_out
@@ -205,8 +215,7 @@ def mdhp_attack_times(strategy, sampler, params, t_range, cap, *, seed: int = 20
                             "than 2^24 candidates")
     if bool((n < 0).any()):
         raise MdhpError(-1, "attack_times: an attack has more injections than its room (cap)")
-    keep = torch.cat([torch.arange(int(off[a]), int(off[a]) + int(n[a])) for a in range(A)]) \
-        if A else torch.zeros(0, dtype=torch.int64)
+    keep = _first_slots(off, n)
     off_c = torch.zeros(A + 1, dtype=torch.int64)
     torch.cumsum(n, 0, out=off_c[1:])
     return off_c.to(dev), t[keep.to(dev)]

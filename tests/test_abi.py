@@ -129,3 +129,14 @@ def test_host_error_paths_of_the_simulator_and_the_lstm():
     assert lib.mdhp_lstm_backward(ctypes.byref(dims), *([None] * 14), None) == -1
     # with B = 0 the weight arrays are still required
     assert lib.mdhp_lstm_backward(ctypes.byref(empty), *([None] * 14), None) == -1
+
+
+def test_first_slots_compaction():
+    """The binding's compaction of per-window rooms to the events drawn."""
+    import torch
+    from paper_2411_10258_amd.api import _first_slots
+    off = torch.tensor([0, 5, 5, 12, 20])
+    n = torch.tensor([3, 0, 7, 2])
+    assert _first_slots(off, n).tolist() == [0, 1, 2, 5, 6, 7, 8, 9, 10, 11, 12, 13]
+    assert _first_slots(torch.tensor([0]), torch.zeros(0, dtype=torch.int64)).numel() == 0
+    assert _first_slots(torch.tensor([0, 4]), torch.tensor([4])).tolist() == [0, 1, 2, 3]
