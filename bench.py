@@ -317,6 +317,7 @@ def bench_lstm(args, dev) -> int:
                                "kind": "oracle",
                                "sample": f"forward+backward of {n} sequences (16 at a time) of "
                                          f"the same workload, {dt:.1f} s, numpy FP64"}
+    out["host"] = host_info()
     print(json.dumps(out), flush=True)
     return 0
 
@@ -383,6 +384,7 @@ def bench_c4(args, dev) -> int:
                                    "log_beta": float(err[:, -1].mean())}},
     }
     net.close()
+    out["host"] = host_info()
     print(json.dumps(out), flush=True)
     return 0
 
@@ -432,6 +434,7 @@ def bench_sim(args, dev) -> int:
                                "cores": threads, "kind": "host generator",
                                "sample": f"the first {k} windows ({int(counts[:k].sum())} "
                                          f"events), {dt:.1f} s"}
+    out["host"] = host_info()
     print(json.dumps(out), flush=True)
     return 0
 
