@@ -20,10 +20,10 @@
 //    and updates their cells in registers;
 //  * backward (lstm_bwd_kernel) runs the steps in reverse, with dz_{t+1} U on
 //    the matrix cores, and writes the pre-activation gradients dz_t over the
-//    saved gates, plus the hks gradient; the weight and input gradients then
-//    are GEMMs over all steps: dX = dZ W, dW = dZ^T X,
-//    dU = sum_t dz_t^T h_{t-1}, db = column sums of dZ, and the Hawkes-gate
-//    weights from dpre = dhks (1 - hks^2).
+//    saved gates, plus the hks gradient and each workgroup's column sums of
+//    dz (db is their sum); the weight and input gradients then are GEMMs
+//    over all steps: dX = dZ W, dW = dZ^T X, dU = sum_t dz_t^T h_{t-1}, and
+//    the Hawkes-gate weights from dpre = dhks (1 - hks^2).
 //
 // MFMA 16x16x4 FP32 operand layout (lane l): A[i = l % 16][k = l / 16],
 // B[k = l / 16][j = l % 16]; result element r: row 4 (l / 16) + r, column
